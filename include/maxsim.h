@@ -1,0 +1,218 @@
+/*
+ * maxsim.h -- C ABI of the MI355X (gfx950) TileMaxSim scoring library.
+ *
+ * The library implements late-interaction MaxSim scoring (Eq. (1) of
+ * "TileMaxSim: IO-Aware GPU MaxSim Scoring with Dimension Tiling and Fused
+ * Product Quantization", arXiv 2606.26439):
+ *
+ *     score(Q, D) = sum_{i < Nq} max_{j < Nd} q_i . d_j
+ *
+ * fused so that every document token is read from HBM once (Sec. 3.2.3 and
+ * Theorem 1), with 128-wide dimension chunks accumulated in FP32 before the
+ * max (Evaluation, "Embedding Dimension Scaling"), PQ scoring through
+ * per-query lookup tables held in LDS (Sec. 4.2-4.3), top-k selection, the
+ * unfused comparator that materialises S = Q D^T (Sec. 2.3, Eq. io_naive),
+ * and the per-token input conversion the precision forms need.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every data pointer is a DEVICE pointer (HBM of the current HIP device)
+ *   owned by the caller. The library never frees or retains it beyond the
+ *   stream-ordered work it enqueues. Descriptor structs are HOST memory and
+ *   are read only during the call.
+ * - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *   stream). Host-visible argument errors return a non-zero status BEFORE
+ *   anything is enqueued; MAXSIM_EHIP reports a failed launch.
+ * - Token sets are CSR-packed: tokens[n_tokens, dim] row-major, row stride
+ *   dim * element_size bytes, base address 16-byte aligned; set s owns rows
+ *   offsets[s] .. offsets[s+1]-1, offsets[0] = 0 and non-decreasing (int64).
+ * - Scores are FP32. A document with no tokens scores -inf (a max over an
+ *   empty set); a query with no tokens scores 0 (an empty sum). Each score is
+ *   produced by exactly one wavefront with a fixed reduction order, so
+ *   results are bit-reproducible run to run and independent of batching.
+ * - The error text of the last failing call on the calling thread is
+ *   returned by maxsim_last_error().
+ */
+#ifndef MAXSIM_H
+#define MAXSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MAXSIM_ABI_VERSION 1
+
+typedef void* maxsim_stream_t; /* hipStream_t */
+
+typedef enum {
+  MAXSIM_OK = 0,
+  MAXSIM_EINVAL = 1,       /* bad pointer, size, alignment or inconsistent descriptor */
+  MAXSIM_EUNSUPPORTED = 2, /* valid request outside what the kernels handle */
+  MAXSIM_EWORKSPACE = 3,   /* workspace missing or smaller than *_workspace_size() */
+  MAXSIM_EHIP = 4          /* a HIP runtime call or kernel launch failed */
+} maxsim_status;
+
+typedef enum {
+  MAXSIM_F32 = 0,
+  MAXSIM_BF16 = 1,
+  MAXSIM_F16 = 2,
+  MAXSIM_F8E4M3 = 3 /* OCP E4M3FN codes with one FP32 power-of-two scale per token */
+} maxsim_dtype;
+
+/*
+ * A CSR set of token-vector sets (documents or queries). Q in R^{Nq x d} and
+ * D in R^{Nd x d} of Eq. (1), one set each.
+ *   dtype     element type of `tokens`.
+ *   dim       d; a multiple of 64, 64 <= dim <= 1024.
+ *   n_sets    number of sets; n_tokens = offsets[n_sets] (host copies, so the
+ *             library needs no device-to-host read).
+ *   max_len   host upper bound on tokens per set. For queries it selects the
+ *             kernel's query-token capacity and must be <= 64; a query that
+ *             exceeds it on the device gets NaN scores.
+ *   scales    FP8 only: [n_tokens] FP32 per-token scales, each a normal power
+ *             of two; the token's value is code * scale. NULL otherwise.
+ */
+typedef struct {
+  int32_t dtype;
+  int32_t dim;
+  int64_t n_sets;
+  int64_t n_tokens;
+  int32_t max_len;
+  int32_t reserved;
+  const void* tokens;
+  const int64_t* offsets;
+  const float* scales;
+} maxsim_csr;
+
+/*
+ * Candidate lists: query a is scored against documents
+ * doc_ids[offsets[a] .. offsets[a+1]-1] (int32 ids into the document set);
+ * n_total = offsets[n_queries] on the host. A NULL maxsim_candidates* means
+ * every query against every document, scores laid out [n_queries, n_docs].
+ * Ids outside [0, n_docs) are the caller's error (not checked on device).
+ */
+typedef struct {
+  const int64_t* offsets;
+  const int32_t* doc_ids;
+  int64_t n_total;
+} maxsim_candidates;
+
+/*
+ * PQ-compressed documents (Sec. 4.1): token t is the concatenation over
+ * m < M of centroid codebooks[m, codes[t, m], :] (dsub values each), so
+ * dim = M * dsub.
+ *   M in {4, 8, 16}; K <= 256; dsub a multiple of 4 with M * dsub <= 256.
+ *   cb_dtype MAXSIM_F16 or MAXSIM_F32 for codebooks[M, K, dsub].
+ *   codes [n_tokens, M] uint8; offsets [n_docs + 1] int64 as for maxsim_csr.
+ */
+typedef struct {
+  int32_t M;
+  int32_t K;
+  int32_t dsub;
+  int32_t cb_dtype;
+  const void* codebooks;
+  const uint8_t* codes;
+  const int64_t* offsets;
+  int64_t n_docs;
+  int64_t n_tokens;
+} maxsim_pq_docs;
+
+int maxsim_abi_version(void);
+const char* maxsim_last_error(void);
+
+/*
+ * Input preparation for the precision forms (Evaluation, "Precision"; FP8 is
+ * this library's addition). Converts src[n_tokens, dim] FP32 into `dtype`:
+ *   BF16 / F16: round to nearest even per element; `scales` must be NULL.
+ *   F8E4M3: per token, s = 2^k with k the smallest integer such that
+ *           max_u |x_u| <= 448 * 2^k (s = 1 for an all-zero token), written to
+ *           scales[t]; codes = E4M3FN(x / s), round to nearest even.
+ *   F32: plain copy.
+ * dst has n_tokens * dim elements of `dtype`.
+ */
+maxsim_status maxsim_quantize(const float* src, int64_t n_tokens, int32_t dim, int32_t dtype,
+                              void* dst, float* scales, maxsim_stream_t stream);
+
+/*
+ * Fused MaxSim (Algorithm 3, "V2-MQ", with BQ = Nq so each document byte is
+ * read once; Theorem 1). Many queries of uneven Nq (<= 64) against ragged
+ * documents in one persistent launch.
+ *   queries, docs  same dtype and dim. For F8E4M3 both carry scales; S_ij is
+ *                  scaled by s_q[i] * s_d[j] (exact, powers of two).
+ *   cand           NULL: scores[a * n_docs + b]; else scores[p] for each pair
+ *                  index p of the candidate lists.
+ *   workspace      maxsim_score_workspace_size() bytes (may be 0 -> NULL ok).
+ */
+size_t maxsim_score_workspace_size(const maxsim_csr* queries, const maxsim_csr* docs,
+                                   const maxsim_candidates* cand);
+maxsim_status maxsim_score(const maxsim_csr* queries, const maxsim_csr* docs,
+                           const maxsim_candidates* cand, float* scores, void* workspace,
+                           size_t ws_bytes, maxsim_stream_t stream);
+
+/*
+ * Unfused comparator (Sec. 2.1 two-step decomposition, Eq. io_naive): first
+ * S = D Q^T for every document token and query token, written to HBM in FP32
+ * inside `workspace`, then a second kernel reads S back for the max over
+ * document tokens and the sum over query tokens. Same arguments and results
+ * as maxsim_score; candidates are not supported (EUNSUPPORTED).
+ */
+size_t maxsim_score_unfused_workspace_size(const maxsim_csr* queries, const maxsim_csr* docs);
+maxsim_status maxsim_score_unfused(const maxsim_csr* queries, const maxsim_csr* docs,
+                                   float* scores, void* workspace, size_t ws_bytes,
+                                   maxsim_stream_t stream);
+
+/*
+ * Fused PQ scoring (Sec. 4.2-4.3): per query, the table
+ * T[i, m, k] = q_i[m*dsub:(m+1)*dsub] . C[m, k] is built in LDS (FP32), then
+ * each document token scores sum_m T[i, m, c_jm], followed by the running
+ * max over tokens and the sum over query tokens. Codes are read from HBM;
+ * decompressed vectors are never written.
+ *   queries  dtype F16 or F32, dim = M * dsub, max_len <= 64.
+ *   cand     as for maxsim_score.
+ */
+size_t maxsim_pq_score_workspace_size(const maxsim_csr* queries, const maxsim_pq_docs* docs,
+                                      const maxsim_candidates* cand);
+maxsim_status maxsim_pq_score(const maxsim_csr* queries, const maxsim_pq_docs* docs,
+                              const maxsim_candidates* cand, float* scores, void* workspace,
+                              size_t ws_bytes, maxsim_stream_t stream);
+
+/*
+ * Top-k per segment (the torch.topk step of the paper's end-to-end pipeline,
+ * Evaluation "End-to-End Retrieval Latency"). Segment s is
+ * scores[seg_offsets[s] .. seg_offsets[s+1]-1]; ids (int32, same indexing)
+ * name the entries, or NULL for the index within the segment. Output rows
+ * out_scores[s * k ..], out_ids[s * k ..] hold the k best entries ordered by
+ * score descending, then id ascending (exact, deterministic); a segment with
+ * fewer than k entries is padded with score -inf and id -1. NaN ranks below
+ * -inf. 1 <= k <= 1024; n_total = seg_offsets[n_segments] (host copy).
+ */
+size_t maxsim_topk_workspace_size(int64_t n_segments, int32_t k);
+maxsim_status maxsim_topk(const float* scores, const int64_t* seg_offsets, int64_t n_segments,
+                          int64_t n_total, const int32_t* ids, int32_t k, float* out_scores,
+                          int32_t* out_ids, void* workspace, size_t ws_bytes,
+                          maxsim_stream_t stream);
+
+/*
+ * Tile/launch-shape autotuner (Evaluation, "Tile Size Sensitivity"): times
+ * every candidate launch configuration of the fused kernel on the given
+ * problem with HIP events (synchronises `stream`), keeps the fastest for the
+ * key (dtype, dim, query-token capacity), and, if cache_path is not NULL,
+ * rewrites that JSON file with every tuned key. maxsim_score then uses the
+ * tuned configuration for matching keys. Writes a one-line JSON report of
+ * the timings to report (if not NULL, up to report_len bytes).
+ */
+maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
+                              const maxsim_candidates* cand, float* scores, void* workspace,
+                              size_t ws_bytes, maxsim_stream_t stream, int32_t reps,
+                              const char* cache_path, char* report, size_t report_len);
+/* Loads tuned configurations written by maxsim_autotune (missing file: OK, no-op). */
+maxsim_status maxsim_load_tune_cache(const char* cache_path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAXSIM_H */

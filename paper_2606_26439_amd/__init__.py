@@ -1,0 +1,11 @@
+"""MI355X (gfx950) TileMaxSim: fused late-interaction MaxSim scoring.
+
+Hand-written HIP kernels behind the C ABI of ``include/maxsim.h``
+(``libmaxsim.so``); this package is the thin ctypes binding plus the serving
+loop built on it. PyTorch provides device memory and streams only.
+
+    from paper_2606_26439_amd import Tokens, quantize, score, topk
+"""
+from ._binding import (DTYPES, ELEM_BYTES, Candidates, MaxSimError, PQDocs, Tokens,  # noqa: F401
+                       autotune, lib, load_tune_cache, pq_score, quantize, score,
+                       score_unfused, topk, topk_workspace_bytes, unfused_workspace_bytes)

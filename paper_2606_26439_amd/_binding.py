@@ -1,0 +1,261 @@
+"""ctypes binding of libmaxsim.so (include/maxsim.h): argument marshalling only.
+
+PyTorch supplies device memory and the current HIP stream; every step of the
+scoring path runs in the library's own HIP kernels. There is no fallback: if
+the library is missing every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmaxsim.so")
+
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2, "fp8": 3}
+TORCH_DTYPES = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16,
+                "fp8": torch.uint8}
+ELEM_BYTES = {"f32": 4, "bf16": 2, "f16": 2, "fp8": 1}
+STATUS = {0: "OK", 1: "EINVAL", 2: "EUNSUPPORTED", 3: "EWORKSPACE", 4: "EHIP"}
+
+
+class MaxSimError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("dim", ctypes.c_int32), ("n_sets", ctypes.c_int64),
+                ("n_tokens", ctypes.c_int64), ("max_len", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tokens", ctypes.c_void_p),
+                ("offsets", ctypes.c_void_p), ("scales", ctypes.c_void_p)]
+
+
+class Cand(ctypes.Structure):
+    _fields_ = [("offsets", ctypes.c_void_p), ("doc_ids", ctypes.c_void_p),
+                ("n_total", ctypes.c_int64)]
+
+
+class PQ(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("K", ctypes.c_int32), ("dsub", ctypes.c_int32),
+                ("cb_dtype", ctypes.c_int32), ("codebooks", ctypes.c_void_p),
+                ("codes", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("n_docs", ctypes.c_int64), ("n_tokens", ctypes.c_int64)]
+
+
+_lib = None
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """The loaded library (loads on first use; torch is imported first so the
+    library binds to the HIP runtime torch already loaded)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(or python -m paper_2606_26439_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.maxsim_abi_version.restype = ctypes.c_int
+    L.maxsim_last_error.restype = ctypes.c_char_p
+    L.maxsim_quantize.argtypes = [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
+                                  _vp]
+    L.maxsim_score_workspace_size.argtypes = [_P(CSR), _P(CSR), _P(Cand)]
+    L.maxsim_score_workspace_size.restype = ctypes.c_size_t
+    L.maxsim_score.argtypes = [_P(CSR), _P(CSR), _P(Cand), _vp, _vp, ctypes.c_size_t, _vp]
+    L.maxsim_score_unfused_workspace_size.argtypes = [_P(CSR), _P(CSR)]
+    L.maxsim_score_unfused_workspace_size.restype = ctypes.c_size_t
+    L.maxsim_score_unfused.argtypes = [_P(CSR), _P(CSR), _vp, _vp, ctypes.c_size_t, _vp]
+    L.maxsim_pq_score_workspace_size.argtypes = [_P(CSR), _P(PQ), _P(Cand)]
+    L.maxsim_pq_score_workspace_size.restype = ctypes.c_size_t
+    L.maxsim_pq_score.argtypes = [_P(CSR), _P(PQ), _P(Cand), _vp, _vp, ctypes.c_size_t, _vp]
+    L.maxsim_topk_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32]
+    L.maxsim_topk_workspace_size.restype = ctypes.c_size_t
+    L.maxsim_topk.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int64, _vp, ctypes.c_int32, _vp,
+                              _vp, _vp, ctypes.c_size_t, _vp]
+    L.maxsim_autotune.argtypes = [_P(CSR), _P(CSR), _P(Cand), _vp, _vp, ctypes.c_size_t, _vp,
+                                  ctypes.c_int32, ctypes.c_char_p, ctypes.c_char_p,
+                                  ctypes.c_size_t]
+    L.maxsim_load_tune_cache.argtypes = [ctypes.c_char_p]
+    for name in ("maxsim_quantize", "maxsim_score", "maxsim_score_unfused", "maxsim_pq_score",
+                 "maxsim_topk", "maxsim_autotune", "maxsim_load_tune_cache"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != 0:
+        raise MaxSimError(st, lib().maxsim_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Tokens:
+    """A CSR set of token-vector sets on the device (documents or queries).
+
+    tokens  [n_tokens, dim] tensor of the element type (uint8 codes for fp8)
+    offsets [n_sets + 1] int64 tensor
+    scales  [n_tokens] float32 (fp8 only)
+    max_len host upper bound on tokens per set (computed if None; queries need it)
+    """
+
+    def __init__(self, tokens, offsets, dtype: str, scales=None, max_len=None):
+        if dtype not in DTYPES:
+            raise ValueError(f"dtype must be one of {list(DTYPES)}")
+        self.tokens, self.offsets, self.scales, self.dtype = tokens, offsets, scales, dtype
+        self.dim = int(tokens.shape[1])
+        self.n_sets = int(offsets.numel()) - 1
+        self.n_tokens = int(tokens.shape[0])
+        if max_len is None:
+            max_len = int((offsets[1:] - offsets[:-1]).max().item()) if self.n_sets > 0 else 0
+        self.max_len = int(max_len)
+
+    def csr(self) -> CSR:
+        return CSR(DTYPES[self.dtype], self.dim, self.n_sets, self.n_tokens, self.max_len, 0,
+                   self.tokens.data_ptr() if self.n_tokens else None, self.offsets.data_ptr(),
+                   self.scales.data_ptr() if self.scales is not None else None)
+
+
+class Candidates:
+    """Per-query candidate lists: offsets [n_queries + 1] int64, doc_ids int32."""
+
+    def __init__(self, offsets, doc_ids):
+        self.offsets, self.doc_ids = offsets, doc_ids
+        self.n_total = int(doc_ids.numel())
+
+    def c(self) -> Cand:
+        return Cand(self.offsets.data_ptr(), self.doc_ids.data_ptr() if self.n_total else None,
+                    self.n_total)
+
+
+class PQDocs:
+    """PQ-compressed documents: codebooks [M, K, dsub] (f16/f32), codes [T, M] uint8."""
+
+    def __init__(self, codebooks, codes, offsets):
+        self.codebooks, self.codes, self.offsets = codebooks, codes, offsets
+        self.M, self.K, self.dsub = (int(x) for x in codebooks.shape)
+        self.n_docs = int(offsets.numel()) - 1
+        self.n_tokens = int(codes.shape[0])
+        self.cb_dtype = {torch.float16: DTYPES["f16"], torch.float32: DTYPES["f32"]}[codebooks.dtype]
+
+    def pq(self) -> PQ:
+        return PQ(self.M, self.K, self.dsub, self.cb_dtype, self.codebooks.data_ptr(),
+                  self.codes.data_ptr() if self.n_tokens else None, self.offsets.data_ptr(),
+                  self.n_docs, self.n_tokens)
+
+
+def _n_pairs(q: Tokens, n_docs: int, cand):
+    return cand.n_total if cand is not None else q.n_sets * n_docs
+
+
+def quantize(x, dtype: str, stream=None):
+    """FP32 [T, d] -> (tokens of `dtype`, per-token scales for fp8 else None)."""
+    T, d = x.shape
+    out = torch.empty((T, d), dtype=TORCH_DTYPES[dtype], device=x.device)
+    sc = torch.empty(T, dtype=torch.float32, device=x.device) if dtype == "fp8" else None
+    _check(lib().maxsim_quantize(_ptr(x), T, d, DTYPES[dtype], _ptr(out), _ptr(sc),
+                                 _stream(stream)))
+    return out, sc
+
+
+def score(q: Tokens, d: Tokens, cand: Candidates = None, out=None, stream=None):
+    """Fused MaxSim scores: [n_q * n_docs] (no candidates) or [cand.n_total]."""
+    n = _n_pairs(q, d.n_sets, cand)
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.float32, device=d.offsets.device)
+    qc, dc = q.csr(), d.csr()
+    cc = cand.c() if cand is not None else None
+    _check(lib().maxsim_score(ctypes.byref(qc), ctypes.byref(dc),
+                              ctypes.byref(cc) if cc is not None else None, _ptr(out), None, 0,
+                              _stream(stream)))
+    return out
+
+
+def unfused_workspace_bytes(q: Tokens, d: Tokens) -> int:
+    qc, dc = q.csr(), d.csr()
+    return int(lib().maxsim_score_unfused_workspace_size(ctypes.byref(qc), ctypes.byref(dc)))
+
+
+def score_unfused(q: Tokens, d: Tokens, out=None, workspace=None, stream=None):
+    """Unfused comparator: S = D Q^T to HBM, then max/sum from HBM."""
+    n = q.n_sets * d.n_sets
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.float32, device=d.offsets.device)
+    need = unfused_workspace_bytes(q, d)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=d.offsets.device)
+    qc, dc = q.csr(), d.csr()
+    _check(lib().maxsim_score_unfused(ctypes.byref(qc), ctypes.byref(dc), _ptr(out),
+                                      _ptr(workspace), workspace.numel(), _stream(stream)))
+    return out
+
+
+def pq_score(q: Tokens, d: PQDocs, cand: Candidates = None, out=None, workspace=None,
+             stream=None):
+    """Fused PQ scores (table in LDS), same layout as score()."""
+    n = _n_pairs(q, d.n_docs, cand)
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.float32, device=d.offsets.device)
+    qc, pc = q.csr(), d.pq()
+    cc = cand.c() if cand is not None else None
+    ccp = ctypes.byref(cc) if cc is not None else None
+    need = int(lib().maxsim_pq_score_workspace_size(ctypes.byref(qc), ctypes.byref(pc), ccp))
+    if workspace is None and need > 0:
+        workspace = torch.empty(need, dtype=torch.uint8, device=d.offsets.device)
+    _check(lib().maxsim_pq_score(ctypes.byref(qc), ctypes.byref(pc), ccp, _ptr(out),
+                                 _ptr(workspace), 0 if workspace is None else workspace.numel(),
+                                 _stream(stream)))
+    return out
+
+
+def topk_workspace_bytes(n_segments: int, k: int) -> int:
+    return int(lib().maxsim_topk_workspace_size(n_segments, k))
+
+
+def topk(scores, seg_offsets, k: int, ids=None, n_total=None, workspace=None, stream=None):
+    """Per-segment top-k by (score desc, id asc): (scores [n_seg, k], ids [n_seg, k])."""
+    n_seg = int(seg_offsets.numel()) - 1
+    n_total = int(scores.numel()) if n_total is None else int(n_total)
+    dev = seg_offsets.device
+    out_s = torch.empty((n_seg, k), dtype=torch.float32, device=dev)
+    out_i = torch.empty((n_seg, k), dtype=torch.int32, device=dev)
+    need = topk_workspace_bytes(n_seg, k)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(lib().maxsim_topk(_ptr(scores), _ptr(seg_offsets), n_seg, n_total, _ptr(ids), k,
+                             _ptr(out_s), _ptr(out_i), _ptr(workspace), workspace.numel(),
+                             _stream(stream)))
+    return out_s, out_i
+
+
+def autotune(q: Tokens, d: Tokens, cand: Candidates = None, reps: int = 10,
+             cache_path: str = None, stream=None) -> dict:
+    """Times every fused launch shape on this problem and keeps the fastest."""
+    n = _n_pairs(q, d.n_sets, cand)
+    out = torch.empty(max(n, 1), dtype=torch.float32, device=d.offsets.device)
+    qc, dc = q.csr(), d.csr()
+    cc = cand.c() if cand is not None else None
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib().maxsim_autotune(ctypes.byref(qc), ctypes.byref(dc),
+                                 ctypes.byref(cc) if cc is not None else None, _ptr(out), None, 0,
+                                 _stream(stream), reps,
+                                 cache_path.encode() if cache_path else None, buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
+def load_tune_cache(path: str):
+    _check(lib().maxsim_load_tune_cache(path.encode()))

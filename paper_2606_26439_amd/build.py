@@ -1,0 +1,64 @@
+"""Builds libmaxsim.so (the gfx950 HIP kernels and the C ABI) in-tree with hipcc.
+
+Every HIP translation unit is compiled for gfx950 only, with packed-FP32
+instruction selection disabled, then linked into one shared library that
+resolves the HIP runtime already loaded by the host process.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT = os.path.join(HERE, "libmaxsim.so")
+BUILD_DIR = os.path.join(HERE, "_build")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+# (source, object name, extra flags); the fused scorer is compiled once per
+# element type so the four instantiation sets build in parallel.
+SOURCES = [("fused_inst.hip", f"fused_dt{t}", [f"-DFUSED_DT={t}"]) for t in range(4)] + [
+    ("fused_dispatch.cpp", "fused_dispatch", []),
+    ("pq.hip", "pq", []),
+    ("topk.hip", "topk", []),
+    ("quantize.hip", "quantize", []),
+    ("api.cpp", "api", []),
+]
+
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
+
+
+def _compile(spec) -> str:
+    src, name, extra = spec
+    obj = os.path.join(BUILD_DIR, name + ".o")
+    cmd = [HIPCC, *COMMON, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    workers = min(len(SOURCES), max(1, min(8, os.cpu_count() or 4)))
+    with cf.ThreadPoolExecutor(workers) as ex:
+        objs = list(ex.map(_compile, SOURCES))
+    tmp = OUT + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, OUT)
+    if verbose:
+        print(f"built {OUT}")
+    return OUT
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

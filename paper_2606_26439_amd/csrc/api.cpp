@@ -1,0 +1,530 @@
+// api.cpp -- the C ABI of include/maxsim.h: argument validation (before any
+// work is enqueued), kernel selection, workspace sizing, error reporting and
+// the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/maxsim.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+maxsim_status fail(maxsim_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+maxsim_status hip_fail(hipError_t e, const char* what) {
+  return fail(MAXSIM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int esize(int dt) { return dt == MAXSIM_F32 ? 4 : (dt == MAXSIM_F8E4M3 ? 1 : 2); }
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+maxsim_status check_csr(const maxsim_csr* c, const char* name, bool is_query) {
+  if (!c) return fail(MAXSIM_EINVAL, "%s: descriptor is NULL", name);
+  if (c->dtype < MAXSIM_F32 || c->dtype > MAXSIM_F8E4M3)
+    return fail(MAXSIM_EINVAL, "%s: unknown dtype %d", name, c->dtype);
+  if (c->dim < 64 || c->dim > 1024 || c->dim % 64 != 0)
+    return fail(MAXSIM_EUNSUPPORTED, "%s: dim %d must be a multiple of 64 in [64, 1024]", name,
+                c->dim);
+  if (c->n_sets < 0 || c->n_tokens < 0)
+    return fail(MAXSIM_EINVAL, "%s: negative n_sets or n_tokens", name);
+  if (c->max_len < 0) return fail(MAXSIM_EINVAL, "%s: negative max_len", name);
+  if (is_query && c->max_len > 64)
+    return fail(MAXSIM_EUNSUPPORTED, "%s: max_len %d exceeds 64 query tokens", name, c->max_len);
+  if (!c->offsets) return fail(MAXSIM_EINVAL, "%s: offsets is NULL", name);
+  if (c->n_tokens > 0 && !c->tokens) return fail(MAXSIM_EINVAL, "%s: tokens is NULL", name);
+  if (c->tokens && !aligned(c->tokens, 16))
+    return fail(MAXSIM_EINVAL, "%s: tokens must be 16-byte aligned", name);
+  if (!aligned(c->offsets, 8)) return fail(MAXSIM_EINVAL, "%s: offsets must be 8-byte aligned", name);
+  if (c->dtype == MAXSIM_F8E4M3 && c->n_tokens > 0 && !c->scales)
+    return fail(MAXSIM_EINVAL, "%s: FP8 tokens need per-token scales", name);
+  return MAXSIM_OK;
+}
+
+int nqb_for(int max_len) { return max_len <= 16 ? 1 : (max_len <= 32 ? 2 : 4); }
+
+struct DevInfo {
+  int cus = 0;
+  size_t max_lds = 0;
+};
+
+DevInfo device_info() {
+  static std::mutex mu;
+  static std::map<int, DevInfo> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  DevInfo d;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) d.cus = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+          hipSuccess && v > 0)
+    d.max_lds = (size_t)v;
+  else
+    d.max_lds = 160 * 1024;
+  if (d.cus <= 0) d.cus = 256;
+  cache[dev] = d;
+  return d;
+}
+
+// ---------------------------------------------------------------- tuning --
+
+struct TuneKey {
+  int dt, dim, nqb;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dt, dim, nqb) < std::tie(o.dt, o.dim, o.nqb);
+  }
+};
+struct FusedCfg {
+  int pf = 4;
+  int nw = 4;
+  int wg_per_cu = 0;  // 0: as many as fit
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, FusedCfg> g_tuned;
+
+FusedCfg default_cfg(int dt) {
+  FusedCfg c;
+  c.pf = dt == MAXSIM_F32 ? 2 : 4;
+  c.nw = 4;
+  c.wg_per_cu = 0;
+  return c;
+}
+
+FusedCfg lookup_cfg(const TuneKey& k) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(k);
+  return it == g_tuned.end() ? default_cfg(k.dt) : it->second;
+}
+
+// ------------------------------------------------------------ fused plan --
+
+struct FusedPlan {
+  FusedParams P{};
+  int dt = 0, nqb = 1, dch = 128;
+  bool qreg = false;
+  size_t lds = 0;
+  int64_t n_pairs = 0;
+};
+
+maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_candidates* cand,
+                         float* scores, FusedPlan& pl) {
+  maxsim_status st = check_csr(q, "queries", true);
+  if (st) return st;
+  if ((st = check_csr(d, "docs", false))) return st;
+  if (q->dtype != d->dtype) return fail(MAXSIM_EINVAL, "queries and docs differ in dtype");
+  if (q->dim != d->dim) return fail(MAXSIM_EINVAL, "queries and docs differ in dim");
+  if (d->n_sets > 0x7fffffffLL) return fail(MAXSIM_EUNSUPPORTED, "more than 2^31-1 documents");
+  int64_t n_pairs;
+  if (cand) {
+    if (cand->n_total < 0) return fail(MAXSIM_EINVAL, "candidates: negative n_total");
+    if (!cand->offsets) return fail(MAXSIM_EINVAL, "candidates: offsets is NULL");
+    if (cand->n_total > 0 && !cand->doc_ids) return fail(MAXSIM_EINVAL, "candidates: doc_ids is NULL");
+    n_pairs = cand->n_total;
+  } else {
+    n_pairs = q->n_sets * d->n_sets;
+  }
+  if (n_pairs > 0 && !scores) return fail(MAXSIM_EINVAL, "scores is NULL");
+  pl.dt = q->dtype;
+  pl.nqb = nqb_for(q->max_len);
+  pl.dch = (q->dim % 128 == 0) ? 128 : 64;
+  const int nch = q->dim / pl.dch;
+  pl.qreg = nch == 1;
+  const int row_bytes = q->dim * esize(q->dtype);
+  pl.lds = (size_t)pl.nqb * 16 * row_bytes;
+  if (pl.lds > device_info().max_lds)
+    return fail(MAXSIM_EUNSUPPORTED, "query block of %zu bytes exceeds LDS", pl.lds);
+  FusedParams& P = pl.P;
+  P.q_tok = (const char*)q->tokens;
+  P.q_off = q->offsets;
+  P.q_scales = q->scales;
+  P.n_q = q->n_sets;
+  P.d_tok = (const char*)d->tokens;
+  P.d_off = d->offsets;
+  P.d_scales = d->scales;
+  P.n_docs = d->n_sets;
+  P.cand_off = cand ? cand->offsets : nullptr;
+  P.cand_ids = cand ? cand->doc_ids : nullptr;
+  P.scores = scores;
+  P.n_pairs = n_pairs;
+  P.tokens_per_query = d->n_tokens;
+  P.dim = q->dim;
+  P.nch = nch;
+  P.row_bytes = row_bytes;
+  pl.n_pairs = n_pairs;
+  return MAXSIM_OK;
+}
+
+maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s) {
+  if (pl.n_pairs == 0) return MAXSIM_OK;
+  FusedFns fns = fused_kernel_fns(pl.dt, pl.nqb, pl.dch, cfg.pf, cfg.nw, pl.qreg);
+  DevInfo di = device_info();
+  int occ = fns.occupancy(pl.lds);
+  if (occ <= 0) return fail(MAXSIM_EHIP, "fused kernel does not fit on a compute unit");
+  int per_cu = cfg.wg_per_cu > 0 ? std::min(cfg.wg_per_cu, occ) : occ;
+  int64_t grid = (int64_t)per_cu * di.cus;
+  int64_t need = (pl.n_pairs + cfg.nw - 1) / cfg.nw;  // at least one pair per wave
+  if (grid > need) grid = need;
+  if (grid < 1) grid = 1;
+  hipError_t e = fns.launch(pl.P, (int)grid, pl.lds, s);
+  if (e != hipSuccess) return hip_fail(e, "fused MaxSim launch");
+  return MAXSIM_OK;
+}
+
+// ------------------------------------------------------------- JSON cache --
+
+std::string cfg_json_all() {
+  std::string out = "{\"version\":1,\"entries\":[";
+  bool first = true;
+  for (auto& kv : g_tuned) {
+    char b[160];
+    snprintf(b, sizeof b, "%s{\"dtype\":%d,\"dim\":%d,\"nqb\":%d,\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d}",
+             first ? "" : ",", kv.first.dt, kv.first.dim, kv.first.nqb, kv.second.pf, kv.second.nw,
+             kv.second.wg_per_cu);
+    out += b;
+    first = false;
+  }
+  out += "]}";
+  return out;
+}
+
+bool json_int(const char* obj, const char* key, int& v) {
+  char pat[32];
+  snprintf(pat, sizeof pat, "\"%s\":", key);
+  const char* p = strstr(obj, pat);
+  if (!p) return false;
+  v = atoi(p + strlen(pat));
+  return true;
+}
+
+}  // namespace
+
+// =================================================================== ABI ==
+
+extern "C" {
+
+int maxsim_abi_version(void) { return MAXSIM_ABI_VERSION; }
+
+const char* maxsim_last_error(void) { return g_err.c_str(); }
+
+maxsim_status maxsim_quantize(const float* src, int64_t n_tokens, int32_t dim, int32_t dtype,
+                              void* dst, float* scales, maxsim_stream_t stream) {
+  if (n_tokens < 0) return fail(MAXSIM_EINVAL, "quantize: negative n_tokens");
+  if (dim < 64 || dim > 1024 || dim % 64 != 0)
+    return fail(MAXSIM_EUNSUPPORTED, "quantize: dim %d must be a multiple of 64 in [64, 1024]", dim);
+  if (dtype < MAXSIM_F32 || dtype > MAXSIM_F8E4M3)
+    return fail(MAXSIM_EINVAL, "quantize: unknown dtype %d", dtype);
+  if (n_tokens == 0) return MAXSIM_OK;
+  if (!src || !dst) return fail(MAXSIM_EINVAL, "quantize: NULL src or dst");
+  if (!aligned(src, 16) || !aligned(dst, 16))
+    return fail(MAXSIM_EINVAL, "quantize: src and dst must be 16-byte aligned");
+  if (dtype == MAXSIM_F8E4M3 && !scales) return fail(MAXSIM_EINVAL, "quantize: FP8 needs scales");
+  if (dtype != MAXSIM_F8E4M3 && scales)
+    return fail(MAXSIM_EINVAL, "quantize: scales only apply to FP8");
+  hipError_t e = launch_quantize(src, n_tokens, dim, dtype, dst, scales, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "quantize launch");
+  return MAXSIM_OK;
+}
+
+size_t maxsim_score_workspace_size(const maxsim_csr*, const maxsim_csr*, const maxsim_candidates*) {
+  return 0;  // the fused scorer keeps everything on chip
+}
+
+maxsim_status maxsim_score(const maxsim_csr* queries, const maxsim_csr* docs,
+                           const maxsim_candidates* cand, float* scores, void* workspace,
+                           size_t ws_bytes, maxsim_stream_t stream) {
+  (void)workspace;
+  (void)ws_bytes;
+  FusedPlan pl;
+  maxsim_status st = plan_fused(queries, docs, cand, scores, pl);
+  if (st) return st;
+  FusedCfg cfg = lookup_cfg({pl.dt, queries->dim, pl.nqb});
+  return run_fused(pl, cfg, (hipStream_t)stream);
+}
+
+size_t maxsim_score_unfused_workspace_size(const maxsim_csr* q, const maxsim_csr* d) {
+  if (!q || !d) return 0;
+  return (size_t)q->n_sets * (size_t)d->n_tokens * (size_t)(nqb_for(q->max_len) * 16) * 4;
+}
+
+maxsim_status maxsim_score_unfused(const maxsim_csr* queries, const maxsim_csr* docs,
+                                   float* scores, void* workspace, size_t ws_bytes,
+                                   maxsim_stream_t stream) {
+  FusedPlan pl;
+  maxsim_status st = plan_fused(queries, docs, nullptr, scores, pl);
+  if (st) return st;
+  size_t need = maxsim_score_unfused_workspace_size(queries, docs);
+  if (need > 0 && (!workspace || ws_bytes < need))
+    return fail(MAXSIM_EWORKSPACE, "unfused: workspace needs %zu bytes", need);
+  if (pl.n_pairs == 0) return MAXSIM_OK;
+  if (queries->n_sets > 65535) return fail(MAXSIM_EUNSUPPORTED, "unfused: at most 65535 queries");
+  DevInfo di = device_info();
+  int64_t tiles = (docs->n_tokens + 15) / 16;
+  int64_t grid = std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, (int64_t)di.cus * 8));
+  hipError_t e = launch_unfused(pl.dt, pl.nqb, pl.dch, pl.P, (float*)workspace, (int)grid, pl.lds,
+                                (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "unfused launch");
+  return MAXSIM_OK;
+}
+
+// ------------------------------------------------------------------ PQ --
+
+namespace {
+struct PqPlan {
+  PqParams P{};
+  size_t lds = 0;
+  size_t ws = 0;
+};
+
+maxsim_status plan_pq(const maxsim_csr* q, const maxsim_pq_docs* d, const maxsim_candidates* cand,
+                      float* scores, PqPlan& pl) {
+  if (!q || !d) return fail(MAXSIM_EINVAL, "pq: NULL descriptor");
+  if (q->dtype != MAXSIM_F16 && q->dtype != MAXSIM_F32)
+    return fail(MAXSIM_EUNSUPPORTED, "pq: queries must be F16 or F32");
+  if (q->n_sets < 0 || q->max_len < 0) return fail(MAXSIM_EINVAL, "pq: negative query sizes");
+  if (q->max_len > 64) return fail(MAXSIM_EUNSUPPORTED, "pq: max_len exceeds 64 query tokens");
+  if (!q->offsets || (q->n_tokens > 0 && !q->tokens)) return fail(MAXSIM_EINVAL, "pq: NULL query arrays");
+  if (d->M != 4 && d->M != 8 && d->M != 16) return fail(MAXSIM_EUNSUPPORTED, "pq: M must be 4, 8 or 16");
+  if (d->K < 1 || d->K > 256) return fail(MAXSIM_EUNSUPPORTED, "pq: K must be in [1, 256]");
+  if (d->dsub < 1 || d->M * d->dsub > 1024) return fail(MAXSIM_EUNSUPPORTED, "pq: bad dsub");
+  if (q->dim != d->M * d->dsub) return fail(MAXSIM_EINVAL, "pq: query dim != M * dsub");
+  if (d->cb_dtype != MAXSIM_F16 && d->cb_dtype != MAXSIM_F32)
+    return fail(MAXSIM_EUNSUPPORTED, "pq: codebooks must be F16 or F32");
+  if (!d->codebooks || !d->offsets || (d->n_tokens > 0 && !d->codes))
+    return fail(MAXSIM_EINVAL, "pq: NULL document arrays");
+  if (d->codes && !aligned(d->codes, d->M)) return fail(MAXSIM_EINVAL, "pq: codes must be M-byte aligned");
+  if (d->n_docs < 0 || d->n_tokens < 0) return fail(MAXSIM_EINVAL, "pq: negative document sizes");
+  int64_t n_pairs;
+  if (cand) {
+    if (!cand->offsets || cand->n_total < 0 || (cand->n_total > 0 && !cand->doc_ids))
+      return fail(MAXSIM_EINVAL, "pq: bad candidates");
+    n_pairs = cand->n_total;
+  } else {
+    n_pairs = q->n_sets * d->n_docs;
+  }
+  if (n_pairs > 0 && !scores) return fail(MAXSIM_EINVAL, "pq: scores is NULL");
+  const size_t lut_row = (size_t)d->M * d->K * 4;  // bytes per query token of table
+  const size_t budget = device_info().max_lds - 4096;
+  int qt = 64;
+  while (qt > 8 && ((size_t)qt * lut_row + (size_t)qt * q->dim * 4 > budget || qt / 2 >= q->max_len))
+    qt /= 2;
+  if ((size_t)qt * lut_row + (size_t)qt * q->dim * 4 > device_info().max_lds)
+    return fail(MAXSIM_EUNSUPPORTED, "pq: table for M=%d K=%d does not fit LDS", d->M, d->K);
+  int n_slices = std::max(1, (q->max_len + qt - 1) / qt);
+  PqParams& P = pl.P;
+  P.q_tok = (const char*)q->tokens;
+  P.q_off = q->offsets;
+  P.n_q = q->n_sets;
+  P.q_f32 = q->dtype == MAXSIM_F32;
+  P.cb_f32 = d->cb_dtype == MAXSIM_F32;
+  P.codebooks = d->codebooks;
+  P.codes = d->codes;
+  P.d_off = d->offsets;
+  P.n_docs = d->n_docs;
+  P.cand_off = cand ? cand->offsets : nullptr;
+  P.cand_ids = cand ? cand->doc_ids : nullptr;
+  P.scores = scores;
+  P.n_pairs = n_pairs;
+  P.tokens_per_query = d->n_tokens;
+  P.M = d->M;
+  P.K = d->K;
+  P.dsub = d->dsub;
+  P.dim = q->dim;
+  P.qt = qt;
+  P.n_slices = n_slices;
+  // enough items to balance ~4 waves of workgroups over the CUs, but chunks
+  // of at least ~512 pairs so the table build stays amortised
+  int64_t base_items = std::max<int64_t>(1, q->n_sets * n_slices);
+  int64_t want = (int64_t)device_info().cus * 4;
+  int64_t per_query_pairs = q->n_sets > 0 ? n_pairs / q->n_sets : 0;
+  int64_t n_chunks = std::max<int64_t>(1, (want + base_items - 1) / base_items);
+  n_chunks = std::min<int64_t>(n_chunks, std::max<int64_t>(1, per_query_pairs / 512));
+  if ((int64_t)n_chunks * base_items > 0x7fffffffLL)
+    return fail(MAXSIM_EUNSUPPORTED, "pq: too many work items");
+  P.n_chunks = (int)n_chunks;
+  pl.lds = ((size_t)d->M * d->K * qt + (size_t)qt * q->dim) * 4;
+  pl.ws = n_slices > 1 ? (size_t)n_slices * (size_t)n_pairs * 4 : 0;
+  return MAXSIM_OK;
+}
+}  // namespace
+
+size_t maxsim_pq_score_workspace_size(const maxsim_csr* queries, const maxsim_pq_docs* docs,
+                                      const maxsim_candidates* cand) {
+  PqPlan pl;
+  std::string saved = g_err;
+  if (plan_pq(queries, docs, cand, (float*)1, pl)) {
+    g_err = saved;
+    return 0;
+  }
+  return pl.ws;
+}
+
+maxsim_status maxsim_pq_score(const maxsim_csr* queries, const maxsim_pq_docs* docs,
+                              const maxsim_candidates* cand, float* scores, void* workspace,
+                              size_t ws_bytes, maxsim_stream_t stream) {
+  PqPlan pl;
+  maxsim_status st = plan_pq(queries, docs, cand, scores, pl);
+  if (st) return st;
+  if (pl.ws > 0 && (!workspace || ws_bytes < pl.ws))
+    return fail(MAXSIM_EWORKSPACE, "pq: workspace needs %zu bytes", pl.ws);
+  if (pl.P.n_pairs == 0) return MAXSIM_OK;
+  pl.P.partial = (float*)workspace;
+  hipError_t e = launch_pq(pl.P, queries->max_len, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pq launch");
+  return MAXSIM_OK;
+}
+
+// --------------------------------------------------------------- top-k --
+
+size_t maxsim_topk_workspace_size(int64_t n_segments, int32_t k) {
+  if (n_segments < 0 || k < 1 || k > 1024) return 0;
+  return topk_ws_bytes(n_segments, k);
+}
+
+maxsim_status maxsim_topk(const float* scores, const int64_t* seg_offsets, int64_t n_segments,
+                          int64_t n_total, const int32_t* ids, int32_t k, float* out_scores,
+                          int32_t* out_ids, void* workspace, size_t ws_bytes,
+                          maxsim_stream_t stream) {
+  if (k < 1 || k > 1024) return fail(MAXSIM_EUNSUPPORTED, "topk: k must be in [1, 1024]");
+  if (n_segments < 0 || n_total < 0) return fail(MAXSIM_EINVAL, "topk: negative sizes");
+  if (n_segments > 65535) return fail(MAXSIM_EUNSUPPORTED, "topk: at most 65535 segments");
+  if (n_segments == 0) return MAXSIM_OK;
+  if (!seg_offsets || !out_scores || !out_ids || (n_total > 0 && !scores))
+    return fail(MAXSIM_EINVAL, "topk: NULL pointer");
+  size_t need = topk_ws_bytes(n_segments, k);
+  if (!workspace || ws_bytes < need) return fail(MAXSIM_EWORKSPACE, "topk: workspace needs %zu bytes", need);
+  hipError_t e = launch_topk(scores, seg_offsets, n_segments, n_total, ids, k, out_scores, out_ids,
+                             workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "topk launch");
+  return MAXSIM_OK;
+}
+
+// ------------------------------------------------------------ autotune --
+
+maxsim_status maxsim_load_tune_cache(const char* path) {
+  if (!path) return fail(MAXSIM_EINVAL, "load_tune_cache: NULL path");
+  FILE* f = fopen(path, "rb");
+  if (!f) return MAXSIM_OK;
+  std::string txt;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+  fclose(f);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  size_t pos = 0;
+  while ((pos = txt.find("{\"dtype\"", pos)) != std::string::npos) {
+    size_t end = txt.find('}', pos);
+    if (end == std::string::npos) break;
+    std::string obj = txt.substr(pos, end - pos + 1);
+    TuneKey k{};
+    FusedCfg c{};
+    if (json_int(obj.c_str(), "dtype", k.dt) && json_int(obj.c_str(), "dim", k.dim) &&
+        json_int(obj.c_str(), "nqb", k.nqb) && json_int(obj.c_str(), "pf", c.pf) &&
+        json_int(obj.c_str(), "nw", c.nw) && json_int(obj.c_str(), "wg_per_cu", c.wg_per_cu)) {
+      if ((c.pf >= 2 && c.pf <= 4) && (c.nw == 4 || c.nw == 8)) g_tuned[k] = c;
+    }
+    pos = end;
+  }
+  return MAXSIM_OK;
+}
+
+maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
+                              const maxsim_candidates* cand, float* scores, void* workspace,
+                              size_t ws_bytes, maxsim_stream_t stream, int32_t reps,
+                              const char* cache_path, char* report, size_t report_len) {
+  (void)workspace;
+  (void)ws_bytes;
+  FusedPlan pl;
+  maxsim_status st = plan_fused(queries, docs, cand, scores, pl);
+  if (st) return st;
+  if (reps < 1) reps = 1;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(MAXSIM_EHIP, "autotune: event creation failed");
+  std::vector<FusedCfg> space;
+  for (int pf : {2, 3, 4})
+    for (int nw : {4, 8})
+      for (int wpc : {0, 1, 2}) {
+        FusedCfg c;
+        c.pf = pf;
+        c.nw = nw;
+        c.wg_per_cu = wpc;
+        space.push_back(c);
+      }
+  std::string rep = "{\"dtype\":" + std::to_string(pl.dt) + ",\"dim\":" +
+                    std::to_string(queries->dim) + ",\"nqb\":" + std::to_string(pl.nqb) +
+                    ",\"trials\":[";
+  float best_ms = 1e30f;
+  FusedCfg best = default_cfg(pl.dt);
+  bool first = true;
+  for (const FusedCfg& c : space) {
+    if (run_fused(pl, c, s)) continue;  // warm-up (also skips shapes that do not fit)
+    (void)hipEventRecord(e0, s);
+    bool ok = true;
+    for (int r = 0; r < reps && ok; ++r) ok = run_fused(pl, c, s) == MAXSIM_OK;
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess || !ok) continue;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= reps;
+    char b[128];
+    snprintf(b, sizeof b, "%s{\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d,\"ms\":%.5f}", first ? "" : ",",
+             c.pf, c.nw, c.wg_per_cu, ms);
+    rep += b;
+    first = false;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  char b[128];
+  snprintf(b, sizeof b, "],\"best\":{\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d,\"ms\":%.5f}}", best.pf,
+           best.nw, best.wg_per_cu, best_ms);
+  rep += b;
+  std::string all;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[{pl.dt, queries->dim, pl.nqb}] = best;
+    all = cfg_json_all();
+  }
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "wb");
+    if (!f) return fail(MAXSIM_EINVAL, "autotune: cannot write %s", cache_path);
+    fputs(all.c_str(), f);
+    fclose(f);
+  }
+  if (report && report_len > 0) {
+    size_t n = std::min(report_len - 1, rep.size());
+    memcpy(report, rep.data(), n);
+    report[n] = 0;
+  }
+  return MAXSIM_OK;
+}
+
+}  // extern "C"

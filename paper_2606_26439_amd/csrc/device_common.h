@@ -1,0 +1,97 @@
+// device_common.h -- shared device-side helpers of the gfx950 MaxSim kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// Element types, same numbering as maxsim_dtype.
+enum : int { DT_F32 = 0, DT_BF16 = 1, DT_F16 = 2, DT_FP8 = 3 };
+
+template <int DT>
+struct elem_size {
+  static constexpr int value = DT == DT_F32 ? 4 : (DT == DT_FP8 ? 1 : 2);
+};
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
+  uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(uint64_t)v, lane);
+  uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), lane);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ float xor_shfl(float v, int m) { return __shfl_xor(v, m, 64); }
+
+// First index i in [0, n] with arr[i] >= key, for a non-decreasing arr of
+// n + 1 entries with arr[n] >= key. Executed by a whole wavefront: each round
+// probes 64 evenly spaced positions and keeps the bracket of the first hit,
+// so a 1M-entry array takes 4 dependent loads instead of 20.
+__device__ __forceinline__ int64_t wave_lower_bound(const int64_t* __restrict__ arr, int64_t n,
+                                                    int64_t key) {
+  const int lane = lane_id();
+  int64_t lo = 0, hi = n;
+  while (hi - lo + 1 > 64) {
+    int64_t step = (hi - lo + 64) / 64;  // ceil((hi - lo + 1) / 64)
+    int64_t pos = lo + step * lane;
+    if (pos > hi) pos = hi;
+    bool pred = arr[pos] >= key;
+    uint64_t mask = __ballot(pred);
+    if (mask & 1ull) return lo;  // arr[lo] >= key
+    if (mask == 0) {
+      lo = lo + step * 63 + 1;
+    } else {
+      int f = __ffsll((unsigned long long)mask) - 1;  // f >= 1
+      int64_t pf = lo + step * f;
+      if (pf > hi) pf = hi;
+      lo = lo + step * (f - 1) + 1;
+      hi = pf;
+    }
+  }
+  int64_t pos = lo + lane;
+  bool pred = pos <= hi && arr[pos < hi ? pos : hi] >= key;
+  uint64_t mask = __ballot(pred);
+  int f = mask ? __ffsll((unsigned long long)mask) - 1 : (int)(hi - lo);
+  return lo + f;
+}
+
+// Last index a in [0, n) with arr[a] <= key for arr non-decreasing of n + 1
+// entries, arr[0] <= key < arr[n]: the set that owns element `key`.
+__device__ __forceinline__ int64_t wave_owner(const int64_t* __restrict__ arr, int64_t n,
+                                              int64_t key) {
+  // first i with arr[i] >= key + 1, minus one
+  return wave_lower_bound(arr, n, key + 1) - 1;
+}
+
+// E8M0 exponent byte of a normal power-of-two float (2^k -> k + 127).
+__device__ __forceinline__ int e8m0_of(float s) { return (int)((__float_as_uint(s) >> 23) & 0xFF); }
+
+// Scalar (SMEM) loads of wave-uniform indices: reading through the constant
+// address space makes the compiler use s_load, whose completion is tracked by
+// lgkmcnt and therefore independent of the vector loads in flight.
+typedef const __attribute__((address_space(4))) int64_t* const_i64_ptr;
+typedef const __attribute__((address_space(4))) int32_t* const_i32_ptr;
+__device__ __forceinline__ int64_t sload_i64(const int64_t* p, int64_t i) {
+  return ((const_i64_ptr)p)[i];
+}
+__device__ __forceinline__ int sload_i32(const int32_t* p, int64_t i) {
+  return ((const_i32_ptr)p)[i];
+}
+
+// 512 zero bytes (one chunk row of the widest element type): the target of the
+// fixed-count loads a wave issues when it has nothing left to load, so those
+// loads never depend on the caller's buffers being non-empty.
+static __device__ __attribute__((aligned(16))) char g_zero_row[512];

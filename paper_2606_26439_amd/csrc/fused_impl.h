@@ -1,0 +1,444 @@
+// fused_impl.h -- fused MaxSim scoring and the unfused (materialised S) comparator.
+//
+// Fused kernel: Algorithm 3 ("V2-MQ") of the paper with the query block equal
+// to the whole query (BQ = Nq), so each document byte crosses HBM once
+// (Theorem 1), re-designed for gfx950:
+//   * a document tile is 16 rows x one d-chunk (DCH = 128, or 64 when d is
+//     not a multiple of 128); lane (r, g) = (lane % 16, lane / 16) loads row r,
+//     bytes [c*64 + g*16, +16) of the chunk for c < NL, straight into the MFMA
+//     A-operand registers: every wave instruction covers 16 aligned 64-byte
+//     segments, and a PF-deep ring of such register buffers keeps
+//     PF * 4 KiB (FP16) per wave in flight;
+//   * rows past a document's end are clamped to its last row: a duplicated
+//     token never changes a max (Eq. 1), costs no HBM traffic (the line is
+//     already in cache) and needs no -inf masking;
+//   * Q lives in LDS (shared by the workgroup) in the MFMA B-operand layout
+//     [query block nb][16-byte column group][lane], or in VGPRs when d fits
+//     one chunk; S_t^T = D_t Q^T runs on v_mfma_f32_16x16x{32 f16/bf16,
+//     128 f8f6f4, 4 f32}; the d-chunks of a tile accumulate into the same
+//     FP32 registers before the max (the paper's dimension tiling);
+//   * FP8: per-token power-of-two scales go into the E8M0 scale operands of
+//     v_mfma_scale_f32_16x16x128_f8f6f4 (doc row scale on A, query token
+//     scale on B), which is exact for powers of two;
+//   * the running max of query token n (= lane % 16 of block nb) is in-lane
+//     over the 4 accumulator rows; at a document's end two xor-shuffles finish
+//     the max over rows and four more sum the query tokens; one lane stores the
+//     score (no atomics, fixed order: bit-reproducible);
+//   * persistent grid: the (query, doc) pair list is cut into token-balanced
+//     contiguous ranges, one per wave (64-ary wave search over the offsets);
+//     a workgroup reloads Q only where its waves' ranges cross a query.
+#pragma once
+#include "device_common.h"
+#include "kernels.h"
+
+namespace fused_detail {
+
+using ::DT_F32;
+using ::DT_BF16;
+using ::DT_F16;
+using ::DT_FP8;
+
+constexpr int F_VALID = 1, F_EMPTY = 2, F_TFIRST = 4, F_TLAST = 8, F_DLAST = 16;
+
+// Position (in flattened tokens) where wave w of W starts.
+__device__ int64_t wave_range_begin(const FusedParams& P, int64_t w, int64_t W) {
+  if (w >= W) return P.n_pairs;
+  if (P.cand_off != nullptr || P.tokens_per_query <= 0) {
+    return (P.n_pairs / W) * w + ((P.n_pairs % W) * w) / W;
+  }
+  const int64_t T = P.tokens_per_query;
+  const int64_t total = P.n_q * T;
+  // tau = floor(w * total / W) without 128-bit arithmetic
+  int64_t tau = (total / W) * w + ((total % W) * w) / W;
+  int64_t a = tau / T;
+  int64_t rem = tau - a * T;
+  int64_t b = wave_lower_bound(P.d_off, P.n_docs, rem);
+  return a * P.n_docs + b;
+}
+
+template <int DT, int NL>
+__device__ __forceinline__ f32x4 mma_step(f32x4 acc, const u32x4 (&a)[NL], const u32x4 (&b)[NL],
+                                          int sa, int sb) {
+  if constexpr (DT == DT_F16) {
+#pragma unroll
+    for (int c = 0; c < NL; ++c)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a[c]),
+                                                   __builtin_bit_cast(f16x8, b[c]), acc, 0, 0, 0);
+  } else if constexpr (DT == DT_BF16) {
+#pragma unroll
+    for (int c = 0; c < NL; ++c)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c]),
+                                                    __builtin_bit_cast(bf16x8, b[c]), acc, 0, 0,
+                                                    0);
+  } else if constexpr (DT == DT_F32) {
+#pragma unroll
+    for (int c = 0; c < NL; ++c) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[c].x), __uint_as_float(b[c].x),
+                                                 acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[c].y), __uint_as_float(b[c].y),
+                                                 acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[c].z), __uint_as_float(b[c].z),
+                                                 acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[c].w), __uint_as_float(b[c].w),
+                                                 acc, 0, 0, 0);
+    }
+  } else {  // FP8: 32 bytes per lane per MFMA; an odd tail is zero-extended
+#pragma unroll
+    for (int c = 0; c < NL; c += 2) {
+      u32x4 a1 = (c + 1 < NL) ? a[c + 1 < NL ? c + 1 : c] : u32x4{0, 0, 0, 0};
+      u32x4 b1 = (c + 1 < NL) ? b[c + 1 < NL ? c + 1 : c] : u32x4{0, 0, 0, 0};
+      i32x8 A = {(int)a[c].x, (int)a[c].y, (int)a[c].z, (int)a[c].w,
+                 (int)a1.x,   (int)a1.y,   (int)a1.z,   (int)a1.w};
+      i32x8 B = {(int)b[c].x, (int)b[c].y, (int)b[c].z, (int)b[c].w,
+                 (int)b1.x,   (int)b1.y,   (int)b1.z,   (int)b1.w};
+      acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(A, B, acc, 0, 0, 0, sa, 0, sb);
+    }
+  }
+  return acc;
+}
+
+// Stage query `a` into LDS in the B-operand layout. Returns Nq (host-trusted
+// capacity is checked by the caller).
+template <int NQB>
+__device__ int stage_query(const FusedParams& P, int64_t a, u32x4* q_lds, int nthreads) {
+  const int64_t q0 = P.q_off[a];
+  const int nq = (int)(P.q_off[a + 1] - q0);
+  const int ncg = P.row_bytes / 64;  // 16-byte column groups per lane-group row
+  const int total = NQB * ncg * 64;
+  const char* qbase = P.q_tok + q0 * P.row_bytes;
+  for (int idx = threadIdx.x; idx < total; idx += nthreads) {
+    int ln = idx & 63, rest = idx >> 6;
+    int cg = rest % ncg, nb = rest / ncg;
+    int row = nb * 16 + (ln & 15);
+    int beta = cg * 4 + (ln >> 4);
+    u32x4 v = {0, 0, 0, 0};
+    if (row < nq) v = *(const u32x4*)(qbase + (int64_t)row * P.row_bytes + beta * 16);
+    q_lds[idx] = v;
+  }
+  return nq;
+}
+
+template <int DT, int NQB, int DCH, int PF, int NW, bool QREG>
+__global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
+  extern __shared__ u32x4 q_lds[];
+  constexpr int ESZ = elem_size<DT>::value;
+  constexpr int CB = DCH * ESZ;  // bytes of one row within one chunk
+  constexpr int NL = CB / 64;    // 16-byte loads per lane per step
+  static_assert(NL >= 1, "chunk too narrow");
+
+  const int lane = lane_id();
+  const int r = lane & 15, g = lane >> 4;
+  const int wave = uniform(threadIdx.x >> 6);
+  const int nch = P.nch;
+  const int ncg = P.row_bytes / 64;
+
+  const int64_t W = (int64_t)gridDim.x * NW;
+  const int64_t wg0 = (int64_t)blockIdx.x * NW;
+  const int64_t my_lo = uniform64(wave_range_begin(P, wg0 + wave, W));
+  const int64_t my_hi = uniform64(wave_range_begin(P, wg0 + wave + 1, W));
+  int64_t pb = uniform64(wave_range_begin(P, wg0, W));
+  const int64_t pe = uniform64(wave_range_begin(P, wg0 + NW, W));
+
+  while (pb < pe) {
+    int64_t a, qend;
+    if (P.cand_off == nullptr) {
+      a = pb / P.n_docs;
+      qend = (a + 1) * P.n_docs;
+    } else {
+      a = uniform64(wave_owner(P.cand_off, P.n_q, pb));
+      qend = P.cand_off[a + 1];
+    }
+    const int64_t se = qend < pe ? qend : pe;
+    __syncthreads();
+    const int nq = uniform(stage_query<NQB>(P, a, q_lds, NW * 64));
+    __syncthreads();
+
+    int64_t lo = my_lo > pb ? my_lo : pb;
+    const int64_t hi = my_hi < se ? my_hi : se;
+    const int64_t pair_base = (P.cand_off == nullptr) ? a * P.n_docs : 0;
+
+    if (nq > NQB * 16) {  // caller's max_len was wrong: poison, never overrun
+      for (int64_t p = lo + lane; p < hi; p += 64) P.scores[p] = __builtin_nanf("");
+      pb = se;
+      continue;
+    }
+
+    // Query operand registers (one d-chunk) and FP8 query scales.
+    u32x4 qreg[QREG ? NQB : 1][NL];
+    if constexpr (QREG) {
+#pragma unroll
+      for (int nb = 0; nb < NQB; ++nb)
+#pragma unroll
+        for (int c = 0; c < NL; ++c) qreg[nb][c] = q_lds[(nb * ncg + c) * 64 + lane];
+    }
+    int qsc[NQB];
+#pragma unroll
+    for (int nb = 0; nb < NQB; ++nb) {
+      qsc[nb] = 127;
+      if constexpr (DT == DT_FP8) {
+        int row = nb * 16 + r;
+        if (row < nq) qsc[nb] = e8m0_of(P.q_scales[P.q_off[a] + row]);
+      }
+    }
+
+    // ---- prefetch cursor over the (pair, tile, chunk) steps of [lo, hi) ----
+    // Document offsets (and candidate ids) are read with scalar loads from
+    // the constant address space, one document ahead: they are counted by
+    // lgkmcnt, so waiting for them never waits for the tile loads in flight.
+    const bool has_cand = P.cand_off != nullptr;
+    const int64_t* __restrict__ doff = P.d_off;
+    auto doc_of = [&](int64_t p, int nxt_id) -> int64_t {
+      return has_cand ? (int64_t)nxt_id : p - pair_base;
+    };
+    int64_t cp = lo;  // cursor pair
+    int64_t ct0 = 0;
+    int cnd = 0, ctile = 0, cchunk = 0;
+    int64_t nx_s = 0, nx_e = 0;  // offsets of pair cp + 1 (raw)
+    int nx2_id = 0;              // candidate id of pair cp + 2
+    if (cp < hi) {
+      int id0 = has_cand ? sload_i32(P.cand_ids, cp) : 0;
+      int64_t b0 = doc_of(cp, id0);
+      ct0 = sload_i64(doff, b0);
+      cnd = (int)(sload_i64(doff, b0 + 1) - ct0);
+      if (cp + 1 < hi) {
+        int id1 = has_cand ? sload_i32(P.cand_ids, cp + 1) : 0;
+        int64_t b1 = doc_of(cp + 1, id1);
+        nx_s = sload_i64(doff, b1);
+        nx_e = sload_i64(doff, b1 + 1);
+      }
+      if (has_cand && cp + 2 < hi) nx2_id = sload_i32(P.cand_ids, cp + 2);
+    }
+
+    auto next_pair = [&]() {
+      ++cp;
+      ctile = 0;
+      cchunk = 0;
+      ct0 = nx_s;
+      cnd = (int)(nx_e - nx_s);
+      if (cp + 1 < hi) {
+        int64_t b1 = doc_of(cp + 1, nx2_id);
+        nx_s = sload_i64(doff, b1);
+        nx_e = sload_i64(doff, b1 + 1);
+        if (has_cand && cp + 2 < hi) nx2_id = sload_i32(P.cand_ids, cp + 2);
+      }
+    };
+
+    u32x4 buf[PF][NL];
+    int bsc[PF];
+    int flags[PF];
+    int64_t fp[PF];
+
+    // Every fill issues exactly NL (+1 for FP8) loads, from a harmless address
+    // when there is nothing left to load, so the compiler's vmcnt accounting
+    // sees a fixed depth of PF steps in flight.
+    auto fill = [&](u32x4 (&bb)[NL], int& sc, int& fl, int64_t& pp) {
+      int f = 0;
+      const char* base = g_zero_row;
+      const float* sptr = (const float*)g_zero_row;
+      pp = cp;
+      if (cp < hi) {
+        if (cnd == 0) {
+          f = F_VALID | F_EMPTY;
+        } else {
+          int row = ctile * 16 + r;
+          row = row < cnd ? row : cnd - 1;
+          const int64_t srow = ct0 + row;
+          base = P.d_tok + srow * P.row_bytes + cchunk * CB + g * 16;
+          if constexpr (DT == DT_FP8) sptr = P.d_scales + srow;
+          f = F_VALID | (cchunk == 0 ? F_TFIRST : 0) | (cchunk << 8);
+          if (cchunk == nch - 1) {
+            f |= F_TLAST;
+            if ((ctile + 1) * 16 >= cnd) f |= F_DLAST;
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NL; ++c) bb[c] = *(const u32x4*)(base + c * 64);
+      if constexpr (DT == DT_FP8) {
+        sc = e8m0_of(*sptr);
+      } else {
+        sc = 127;
+      }
+      fl = f;
+      if (cp < hi) {
+        if (cnd == 0) {
+          next_pair();
+        } else if (++cchunk == nch) {
+          cchunk = 0;
+          if (++ctile * 16 >= cnd) next_pair();
+        }
+      }
+    };
+
+    f32x4 acc[NQB];
+    float mx[NQB];
+#pragma unroll
+    for (int nb = 0; nb < NQB; ++nb) {
+      acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      mx[nb] = -__builtin_inff();
+    }
+
+    auto finalize = [&](int64_t pp) {
+      float tot = 0.f;
+#pragma unroll
+      for (int nb = 0; nb < NQB; ++nb) {
+        float v = mx[nb];
+        v = fmaxf(v, xor_shfl(v, 16));
+        v = fmaxf(v, xor_shfl(v, 32));
+        tot += v;
+        mx[nb] = -__builtin_inff();
+      }
+      tot += xor_shfl(tot, 8);
+      tot += xor_shfl(tot, 4);
+      tot += xor_shfl(tot, 2);
+      tot += xor_shfl(tot, 1);
+      if (lane == 0) P.scores[pp] = tot;
+    };
+
+    auto consume = [&](const u32x4 (&bb)[NL], int sc, int fl, int64_t pp) {
+      if (!(fl & F_VALID)) return;
+      if (fl & F_EMPTY) {
+        if (lane == 0) P.scores[pp] = nq == 0 ? 0.f : -__builtin_inff();
+        return;
+      }
+      if constexpr (QREG) {
+        // one chunk per tile: every step starts and ends a tile
+#pragma unroll
+        for (int nb = 0; nb < NQB; ++nb) {
+          f32x4 t = mma_step<DT, NL>(f32x4{0.f, 0.f, 0.f, 0.f}, bb, qreg[nb], sc, qsc[nb]);
+          mx[nb] = fmaxf(mx[nb], fmaxf(fmaxf(t.x, t.y), fmaxf(t.z, t.w)));
+        }
+      } else {
+        const int chunk = fl >> 8;
+        const bool first = (fl & F_TFIRST) != 0;
+#pragma unroll
+        for (int nb = 0; nb < NQB; ++nb) {
+          u32x4 qb[NL];
+#pragma unroll
+          for (int c = 0; c < NL; ++c) qb[c] = q_lds[(nb * ncg + chunk * NL + c) * 64 + lane];
+          f32x4 base = first ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[nb];
+          acc[nb] = mma_step<DT, NL>(base, bb, qb, sc, qsc[nb]);
+        }
+        if (fl & F_TLAST) {
+#pragma unroll
+          for (int nb = 0; nb < NQB; ++nb) {
+            f32x4 t = acc[nb];
+            mx[nb] = fmaxf(mx[nb], fmaxf(fmaxf(t.x, t.y), fmaxf(t.z, t.w)));
+          }
+        }
+      }
+      if (fl & F_DLAST) finalize(pp);
+    };
+
+#pragma unroll
+    for (int s = 0; s < PF; ++s) fill(buf[s], bsc[s], flags[s], fp[s]);
+
+    if (flags[0] & F_VALID) {
+      while (true) {
+#pragma unroll
+        for (int s = 0; s < PF; ++s) {
+          consume(buf[s], bsc[s], flags[s], fp[s]);
+          fill(buf[s], bsc[s], flags[s], fp[s]);
+        }
+        // slots are filled in order: an invalid refill of slot 0 means the
+        // cursor was exhausted before this round's refills, and every valid
+        // slot has now been consumed
+        if (!(flags[0] & F_VALID)) break;
+      }
+    }
+    pb = se;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Unfused comparator, step 1: S[a][t][n] = sum_k d_tk q_an (FP32, to HBM).
+// One wave per 16-row tile of the document tokens, Q staged in LDS as above.
+// ---------------------------------------------------------------------------
+template <int DT, int NQB, int DCH, int NW>
+__global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, float* S) {
+  extern __shared__ u32x4 q_lds[];
+  constexpr int ESZ = elem_size<DT>::value;
+  constexpr int CB = DCH * ESZ;
+  constexpr int NL = CB / 64;
+  constexpr int NQP = NQB * 16;
+  const int lane = lane_id();
+  const int r = lane & 15, g = lane >> 4;
+  const int wave = uniform(threadIdx.x >> 6);
+  const int64_t a = blockIdx.y;
+  const int64_t T = P.tokens_per_query;
+  const int64_t ntiles = (T + 15) / 16;
+  const int ncg = P.row_bytes / 64;
+
+  const int nq = uniform(stage_query<NQB>(P, a, q_lds, NW * 64));
+  __syncthreads();
+  int qsc[NQB];
+#pragma unroll
+  for (int nb = 0; nb < NQB; ++nb) {
+    qsc[nb] = 127;
+    if constexpr (DT == DT_FP8) {
+      int row = nb * 16 + r;
+      if (row < nq) qsc[nb] = e8m0_of(P.q_scales[P.q_off[a] + row]);
+    }
+  }
+  float* Sa = S + a * T * NQP;
+  for (int64_t tile = (int64_t)blockIdx.x * NW + wave; tile < ntiles;
+       tile += (int64_t)gridDim.x * NW) {
+    int64_t row = tile * 16 + r;
+    if (row > T - 1) row = T - 1;
+    int sc = 127;
+    if constexpr (DT == DT_FP8) sc = e8m0_of(P.d_scales[row]);
+    f32x4 acc[NQB];
+#pragma unroll
+    for (int nb = 0; nb < NQB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int chunk = 0; chunk < P.nch; ++chunk) {
+      u32x4 bb[NL];
+      const char* base = P.d_tok + row * P.row_bytes + chunk * CB + g * 16;
+#pragma unroll
+      for (int c = 0; c < NL; ++c) bb[c] = *(const u32x4*)(base + c * 64);
+#pragma unroll
+      for (int nb = 0; nb < NQB; ++nb) {
+        u32x4 qb[NL];
+#pragma unroll
+        for (int c = 0; c < NL; ++c) qb[c] = q_lds[(nb * ncg + chunk * NL + c) * 64 + lane];
+        acc[nb] = mma_step<DT, NL>(acc[nb], bb, qb, sc, qsc[nb]);
+      }
+    }
+    // lane holds S rows 4g..4g+3 of column nb*16 + r
+#pragma unroll
+    for (int nb = 0; nb < NQB; ++nb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int64_t orow = tile * 16 + 4 * g + i;
+        if (orow < T) Sa[orow * NQP + nb * 16 + r] = acc[nb][i];
+      }
+    }
+  }
+}
+
+// Unfused comparator, step 2: read S back, max over each document's rows,
+// sum over the query tokens. One wave per (query, doc) pair.
+template <int NQP>
+__global__ __launch_bounds__(256) void seg_maxsum_kernel(FusedParams P, const float* S) {
+  constexpr int RPI = 64 / NQP;  // rows per iteration
+  const int lane = lane_id();
+  const int col = lane % NQP, rsub = lane / NQP;
+  const int64_t T = P.tokens_per_query;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); p < P.n_pairs; p += nw) {
+    int64_t a = p / P.n_docs, b = p - a * P.n_docs;
+    int nq = (int)(P.q_off[a + 1] - P.q_off[a]);
+    int64_t t0 = P.d_off[b], t1 = P.d_off[b + 1];
+    const float* Sa = S + a * T * NQP;
+    float m = -__builtin_inff();
+    for (int64_t t = t0 + rsub; t < t1; t += RPI) m = fmaxf(m, Sa[t * NQP + col]);
+#pragma unroll
+    for (int off = NQP; off < 64; off <<= 1) m = fmaxf(m, xor_shfl(m, off));
+    float v = (col < NQP) ? m : 0.f;
+#pragma unroll
+    for (int off = NQP / 2; off >= 1; off >>= 1) v += xor_shfl(v, off);
+    if (lane == 0) P.scores[p] = (nq == 0) ? 0.f : (t1 == t0 ? -__builtin_inff() : v);
+  }
+}
+
+}  // namespace fused_detail
+

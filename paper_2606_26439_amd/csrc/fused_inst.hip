@@ -1,0 +1,104 @@
+// fused_inst.hip -- host launchers of the fused scorer and of the unfused
+// comparator for one element type. The build compiles this file once per
+// type with -DFUSED_DT=<maxsim_dtype>, so the four types compile in parallel.
+#include "fused_impl.h"
+
+#ifndef FUSED_DT
+#error "FUSED_DT must be defined"
+#endif
+
+namespace {
+
+constexpr int DT = FUSED_DT;
+
+template <int NQB, int DCH, int PF, int NW, bool QREG>
+hipError_t launch_fused_t(const FusedParams& P, int grid, size_t lds, hipStream_t s) {
+  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QREG>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k, dim3(grid), dim3(NW * 64), lds, s, P);
+  return hipGetLastError();
+}
+
+template <int NQB, int DCH, int PF, int NW, bool QREG>
+int occupancy_fused_t(size_t lds) {
+  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QREG>;
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+          hipSuccess)
+    return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, NW * 64, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+template <int NQB, int DCH, int PF, int NW>
+FusedFns pick_q(bool qreg) {
+  if (qreg) return {launch_fused_t<NQB, DCH, PF, NW, true>, occupancy_fused_t<NQB, DCH, PF, NW, true>};
+  return {launch_fused_t<NQB, DCH, PF, NW, false>, occupancy_fused_t<NQB, DCH, PF, NW, false>};
+}
+
+template <int NQB, int DCH, int PF>
+FusedFns pick_nw(int nw, bool qreg) {
+  return nw == 8 ? pick_q<NQB, DCH, PF, 8>(qreg) : pick_q<NQB, DCH, PF, 4>(qreg);
+}
+
+template <int NQB, int DCH>
+FusedFns pick_pf(int pf, int nw, bool qreg) {
+  if (pf == 2) return pick_nw<NQB, DCH, 2>(nw, qreg);
+  if (pf == 3) return pick_nw<NQB, DCH, 3>(nw, qreg);
+  return pick_nw<NQB, DCH, 4>(nw, qreg);
+}
+
+template <int NQB>
+FusedFns pick_dch(int dch, int pf, int nw, bool qreg) {
+  return dch == 64 ? pick_pf<NQB, 64>(pf, nw, qreg) : pick_pf<NQB, 128>(pf, nw, qreg);
+}
+
+template <int NQB, int DCH>
+hipError_t launch_unfused_t(const FusedParams& P, float* S, int grid, size_t lds, hipStream_t s) {
+  auto k1 = fused_detail::sim_matrix_kernel<DT, NQB, DCH, 4>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k1,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k1, dim3(grid, (unsigned)P.n_q), dim3(256), lds, s, P, S);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  constexpr int NQP = NQB * 16;
+  int64_t blocks = (P.n_pairs + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(fused_detail::seg_maxsum_kernel<NQP>, dim3((unsigned)blocks), dim3(256), 0, s,
+                     P, (const float*)S);
+  return hipGetLastError();
+}
+
+template <int NQB>
+hipError_t unfused_dch(const FusedParams& P, float* S, int grid, size_t lds, int dch,
+                       hipStream_t s) {
+  return dch == 64 ? launch_unfused_t<NQB, 64>(P, S, grid, lds, s)
+                   : launch_unfused_t<NQB, 128>(P, S, grid, lds, s);
+}
+
+}  // namespace
+
+#define CAT2(a, b) a##b
+#define CAT(a, b) CAT2(a, b)
+
+FusedFns CAT(fused_kernel_fns_, FUSED_DT)(int nqb, int dch, int pf, int nw, bool qreg) {
+  if (nqb == 1) return pick_dch<1>(dch, pf, nw, qreg);
+  if (nqb == 2) return pick_dch<2>(dch, pf, nw, qreg);
+  return pick_dch<4>(dch, pf, nw, qreg);
+}
+
+hipError_t CAT(launch_unfused_, FUSED_DT)(int nqb, int dch, const FusedParams& P, float* S,
+                                           int grid, size_t lds, hipStream_t s) {
+  if (nqb == 1) return unfused_dch<1>(P, S, grid, lds, dch, s);
+  if (nqb == 2) return unfused_dch<2>(P, S, grid, lds, dch, s);
+  return unfused_dch<4>(P, S, grid, lds, dch, s);
+}

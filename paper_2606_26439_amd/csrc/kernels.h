@@ -1,0 +1,80 @@
+// kernels.h -- host-visible launch interfaces of the kernel translation units.
+// Only the library's own sources include this header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+// Arguments of the fused scorer and the unfused comparator (device pointers).
+struct FusedParams {
+  const char* q_tok;
+  const int64_t* q_off;
+  const float* q_scales;
+  int64_t n_q;
+  const char* d_tok;
+  const int64_t* d_off;
+  const float* d_scales;
+  int64_t n_docs;
+  const int64_t* cand_off;  // nullptr: every query against every doc
+  const int32_t* cand_ids;
+  float* scores;
+  int64_t n_pairs;           // number of (query, doc) scores
+  int64_t tokens_per_query;  // d_off[n_docs] (host copy)
+  int32_t dim;
+  int32_t nch;        // dim / DCH
+  int32_t row_bytes;  // dim * element size
+  int32_t pad;
+};
+
+typedef hipError_t (*fused_launch_fn)(const FusedParams&, int grid, size_t lds, hipStream_t);
+typedef int (*fused_occ_fn)(size_t lds);
+struct FusedFns {
+  fused_launch_fn launch;
+  fused_occ_fn occupancy;
+};
+
+// dt: maxsim_dtype; nqb: query blocks of 16 (1, 2, 4); dch: 64 or 128;
+// pf: prefetch depth (2, 3, 4); nw: waves per workgroup (4, 8); qreg: Q in VGPRs.
+FusedFns fused_kernel_fns(int dt, int nqb, int dch, int pf, int nw, bool qreg);
+
+hipError_t launch_unfused(int dt, int nqb, int dch, const FusedParams& P, float* S, int grid,
+                          size_t lds, hipStream_t s);
+
+// ---- PQ ----
+struct PqParams {
+  const char* q_tok;  // F16 or F32 query tokens
+  const int64_t* q_off;
+  int64_t n_q;
+  int32_t q_f32;     // 1: FP32 query tokens, 0: FP16
+  int32_t cb_f32;    // 1: FP32 codebooks, 0: FP16
+  const void* codebooks;  // [M, K, dsub]
+  const uint8_t* codes;   // [T, M]
+  const int64_t* d_off;
+  int64_t n_docs;
+  const int64_t* cand_off;
+  const int32_t* cand_ids;
+  float* scores;    // final scores
+  float* partial;   // [n_slices, n_pairs] when n_slices > 1, else nullptr
+  int64_t n_pairs;
+  int64_t tokens_per_query;
+  int32_t M, K, dsub, dim;
+  int32_t qt;        // query tokens per slice (LUT rows)
+  int32_t n_slices;  // ceil(max Nq / qt)
+  int32_t n_chunks;  // doc-range chunks per (query, slice)
+  int32_t pad;
+};
+hipError_t launch_pq(const PqParams& P, int max_nq, hipStream_t s);
+
+// ---- top-k ----
+hipError_t launch_topk(const float* scores, const int64_t* seg_off, int64_t n_seg, int64_t n_total,
+                       const int32_t* ids, int k, float* out_scores, int32_t* out_ids, void* ws,
+                       hipStream_t s);
+size_t topk_ws_bytes(int64_t n_seg, int k);
+
+// ---- input conversion ----
+hipError_t launch_quantize(const float* src, int64_t n_tokens, int dim, int dt, void* dst,
+                           float* scales, hipStream_t s);
+
+// ---- device properties ----
+int device_cu_count();

@@ -1,0 +1,45 @@
+"""Shared helpers of the GPU tests (not collected by pytest)."""
+import numpy as np
+import torch
+
+import oracle
+import paper_2606_26439_amd as M
+
+# Kernel-correctness gate against O1 (the exact values the GPU receives):
+# FP32 accumulation of exact products, |gpu - O1| <= 1e-5 * max(|O1|, 1).
+REL_TOL = 1e-5
+# Precision-form bounds against O2 (the FP32 values before rounding).
+O2_TOL = {"f32": None, "bf16": 2e-2, "f16": 2e-2, "fp8": 6e-2}
+
+
+def dev(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def device_tokens(x_f32, off, dtype, max_len=None):
+    """Upload FP32 tokens and convert them on the device with the library's kernel."""
+    x = dev(np.ascontiguousarray(x_f32, np.float32))
+    tok, sc = M.quantize(x, dtype)
+    return M.Tokens(tok, dev(np.asarray(off, np.int64)), dtype, sc, max_len)
+
+
+def assert_close_o1(got, want, what=""):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    assert got.shape == want.shape, (got.shape, want.shape)
+    inf = ~np.isfinite(want)
+    assert np.array_equal(got[inf], want[inf]), f"{what}: non-finite scores differ"
+    g, w = got[~inf], want[~inf]
+    if g.size:
+        err = np.abs(g - w) / np.maximum(np.abs(w), 1.0)
+        i = int(np.argmax(err))
+        assert err[i] <= REL_TOL, f"{what}: max rel err {err[i]:.3e} at {i}: {g[i]} vs {w[i]}"
+
+
+def o1_scores(q, q_off, d, d_off, dtype, cand_off=None, cand_ids=None):
+    qv, _ = oracle.exact_values(q, dtype)
+    dv, _ = oracle.exact_values(d, dtype)
+    return oracle.maxsim(qv, q_off, dv, d_off, cand_off, cand_ids)

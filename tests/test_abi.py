@@ -1,0 +1,87 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared entry
+point, and rejects invalid host-visible arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+import torch  # noqa: F401  (binds the library to torch's HIP runtime)
+
+import paper_2606_26439_amd as M
+from paper_2606_26439_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "maxsim.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(maxsim_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 13
+    L = M.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.maxsim_abi_version() == 1
+
+
+def _csr(dtype=2, dim=128, n_sets=1, n_tokens=4, max_len=4, tokens=16, offsets=16, scales=None):
+    return B.CSR(dtype, dim, n_sets, n_tokens, max_len, 0, tokens, offsets, scales)
+
+
+@pytest.mark.parametrize("q,d,code", [
+    (dict(dim=96), dict(dim=96), 2),                  # dim not a multiple of 64
+    (dict(dtype=7), dict(), 1),                       # unknown dtype
+    (dict(max_len=65), dict(), 2),                    # too many query tokens
+    (dict(), dict(dim=256), 1),                       # dims differ
+    (dict(dtype=1), dict(), 1),                       # dtypes differ
+    (dict(tokens=8), dict(), 1),                      # misaligned tokens
+    (dict(offsets=None), dict(), 1),                  # NULL offsets
+    (dict(dtype=3), dict(dtype=3), 1),                # FP8 without scales
+    (dict(n_sets=-1), dict(), 1),                     # negative size
+])
+def test_score_rejects_bad_arguments(q, d, code):
+    L = M.lib()
+    qc, dc = _csr(**q), _csr(**d)
+    st = L.maxsim_score(ctypes.byref(qc), ctypes.byref(dc), None, ctypes.c_void_p(16), None, 0,
+                        None)
+    assert st == code, L.maxsim_last_error()
+    assert L.maxsim_last_error()
+
+
+def test_topk_and_quantize_validation():
+    L = M.lib()
+    assert L.maxsim_topk(None, ctypes.c_void_p(8), 1, 10, None, 0, None, None, None, 0, None) == 2
+    assert L.maxsim_topk(None, ctypes.c_void_p(8), 1, 10, None, 5, ctypes.c_void_p(8),
+                         ctypes.c_void_p(8), None, 0, None) == 1  # NULL scores with n_total > 0
+    assert L.maxsim_topk(ctypes.c_void_p(8), ctypes.c_void_p(8), 1, 10, None, 5,
+                         ctypes.c_void_p(8), ctypes.c_void_p(8), None, 0, None) == 3  # workspace
+    assert L.maxsim_topk_workspace_size(4, 100) > 4 * 100 * 8
+    assert L.maxsim_quantize(ctypes.c_void_p(16), 4, 100, 2, ctypes.c_void_p(16), None, None) == 2
+    assert L.maxsim_quantize(ctypes.c_void_p(16), 4, 128, 3, ctypes.c_void_p(16), None, None) == 1
+    assert L.maxsim_quantize(ctypes.c_void_p(16), 4, 128, 2, ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), None) == 1
+
+
+def test_pq_and_unfused_validation():
+    L = M.lib()
+    qc = _csr(dim=128)
+    pq = B.PQ(8, 256, 16, 2, 16, 16, 16, 10, 100)
+    bad = B.PQ(6, 256, 16, 2, 16, 16, 16, 10, 100)
+    assert L.maxsim_pq_score(ctypes.byref(qc), ctypes.byref(bad), None, ctypes.c_void_p(16), None,
+                             0, None) == 2
+    qbf = _csr(dtype=1, dim=128)
+    assert L.maxsim_pq_score(ctypes.byref(qbf), ctypes.byref(pq), None, ctypes.c_void_p(16), None,
+                             0, None) == 2
+    dc = _csr(n_tokens=1000)
+    need = L.maxsim_score_unfused_workspace_size(ctypes.byref(qc), ctypes.byref(dc))
+    assert need == 1 * 1000 * 16 * 4
+    assert L.maxsim_score_unfused(ctypes.byref(qc), ctypes.byref(dc), ctypes.c_void_p(16), None, 0,
+                                  None) == 3
+
+
+def test_missing_tune_cache_is_a_no_op(tmp_path):
+    assert M.lib().maxsim_load_tune_cache(str(tmp_path / "none.json").encode()) == 0

@@ -1,0 +1,255 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Sizes keep the oracle to seconds while spanning several 16-row tiles, ragged
+tails, empty documents, every query-token capacity and every d-chunk width.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2606_26439_amd as M
+import workloads as W
+from tests._gpu import assert_close_o1, dev, device_tokens, o1_scores
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = ["f32", "bf16", "f16", "fp8"]
+
+
+def _ragged(n_docs, dim, seed, nq_lens, empty_every=0):
+    lens = W.doc_lengths(n_docs, seed)
+    if empty_every:
+        lens[::empty_every] = 0
+    lens[1] = 1
+    lens[2] = 17  # one full tile + a one-row tail
+    d_off = W.offsets_from_lengths(lens)
+    g = W.rng(seed + 1)
+    d = W.unit_tokens(int(d_off[-1]), dim, g)
+    q_off = W.offsets_from_lengths(nq_lens)
+    q = W.unit_tokens(int(q_off[-1]), dim, g)
+    return q, q_off, d, d_off
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("dim", [64, 128, 768])
+def test_quantize_bit_exact(dtype, dim):
+    x = W.unit_tokens(1001, dim, W.rng(dim))
+    x[5] = 0.0  # all-zero token: scale 1
+    x[7] *= 300.0  # large values
+    tok, sc = M.quantize(dev(x), dtype)
+    torch.cuda.synchronize()
+    _, payload = oracle.exact_values(x, dtype)
+    if dtype == "f32":
+        assert np.array_equal(tok.cpu().numpy().view(np.uint32), x.view(np.uint32))
+    elif dtype in ("bf16", "f16"):
+        got = tok.view(torch.int16).cpu().numpy().view(np.uint16)
+        assert np.array_equal(got, payload[0])
+    else:
+        assert np.array_equal(tok.cpu().numpy(), payload[0])
+        assert np.array_equal(sc.cpu().numpy(), payload[1])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("dim", [64, 128, 256, 768])
+def test_fused_all_docs(dtype, dim):
+    nq_lens = [32, 5, 17] if dim <= 256 else [32, 3]
+    q, q_off, d, d_off = _ragged(150, dim, seed=dim + 3, nq_lens=nq_lens, empty_every=37)
+    Q = device_tokens(q, q_off, dtype)
+    D = device_tokens(d, d_off, dtype)
+    got = M.score(Q, D).cpu().numpy()
+    want = o1_scores(q, q_off, d, d_off, dtype)
+    assert_close_o1(got, want, f"{dtype} d={dim}")
+
+
+@pytest.mark.parametrize("nq", [1, 16, 31, 33, 48, 64])
+def test_fused_query_capacities(nq):
+    q, q_off, d, d_off = _ragged(120, 128, seed=nq, nq_lens=[nq, max(1, nq // 2)])
+    Q = device_tokens(q, q_off, "f16")
+    D = device_tokens(d, d_off, "f16")
+    assert_close_o1(M.score(Q, D).cpu().numpy(), o1_scores(q, q_off, d, d_off, "f16"), f"nq={nq}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_fused_candidates(dtype):
+    q, q_off, d, d_off = _ragged(400, 128, seed=11, nq_lens=[8, 64, 20, 1, 40], empty_every=50)
+    cand_off, cand_ids = W.candidates(5, 400, seed=4, size_range=(10, 300))
+    # a query with no candidates and a repeated id
+    sizes = np.diff(cand_off)
+    sizes[3] = 0
+    ids = [cand_ids[cand_off[a]:cand_off[a + 1]] for a in range(5)]
+    ids[3] = ids[3][:0]
+    ids[1] = np.concatenate([ids[1], ids[1][:3]])
+    cand_ids = np.concatenate(ids).astype(np.int32)
+    cand_off = W.offsets_from_lengths([len(x) for x in ids])
+    Q = device_tokens(q, q_off, dtype)
+    D = device_tokens(d, d_off, dtype)
+    C = M.Candidates(dev(cand_off), dev(cand_ids))
+    got = M.score(Q, D, C).cpu().numpy()
+    want = o1_scores(q, q_off, d, d_off, dtype, cand_off, cand_ids)
+    assert_close_o1(got, want, f"{dtype} candidates")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_query_inside_doc_scores_exactly_nq(dtype):
+    # Dyadic unit vectors are exact in every format, q.q = 1 exactly and every
+    # other dot is < 1, so a document holding every query token scores Nq.
+    nq = 24
+    q = W.dyadic_unit_vectors(nq, 128, seed=1)
+    docs = []
+    for b in range(40):
+        other = W.dyadic_unit_vectors(30, 128, seed=100 + b)
+        sel = np.random.default_rng(b).permutation(nq)[: (nq if b % 2 == 0 else nq // 2)]
+        docs.append(np.concatenate([other[:b % 30], q[sel], other[b % 30:]]))
+    d_off = W.offsets_from_lengths([len(x) for x in docs])
+    d = np.concatenate(docs)
+    Q = device_tokens(q, [0, nq], dtype)
+    D = device_tokens(d, d_off, dtype)
+    got = M.score(Q, D).cpu().numpy()
+    assert np.all(got[0::2] == float(nq)), got[0::2]
+    want = o1_scores(q, [0, nq], d, d_off, dtype)
+    assert_close_o1(got, want, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_doc_token_permutation_is_bit_identical(dtype):
+    q, q_off, d, d_off = _ragged(60, 128, seed=5, nq_lens=[32])
+    g = W.rng(9)
+    dp = d.copy()
+    for b in range(60):
+        s, e = d_off[b], d_off[b + 1]
+        dp[s:e] = d[s:e][g.permutation(e - s)]
+    Q = device_tokens(q, q_off, dtype)
+    a = M.score(Q, device_tokens(d, d_off, dtype)).cpu().numpy()
+    b = M.score(Q, device_tokens(dp, d_off, dtype)).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16", "f32"])
+def test_zero_extended_dimension_is_bit_identical(dtype):
+    # Dimension tiling accumulates the 128-wide chunks into the same FP32
+    # registers; zero chunks add exact zeros, so the result cannot change.
+    q, q_off, d, d_off = _ragged(80, 128, seed=21, nq_lens=[32, 9])
+    base = M.score(device_tokens(q, q_off, dtype), device_tokens(d, d_off, dtype)).cpu().numpy()
+    for ext in (128, 384, 640):
+        qz = np.concatenate([q, np.zeros((len(q), ext), np.float32)], axis=1)
+        dz = np.concatenate([d, np.zeros((len(d), ext), np.float32)], axis=1)
+        got = M.score(device_tokens(qz, q_off, dtype), device_tokens(dz, d_off, dtype))
+        assert np.array_equal(got.cpu().numpy(), base), ext
+
+
+def test_scores_do_not_depend_on_launch_shape():
+    q, q_off, d, d_off = _ragged(300, 128, seed=31, nq_lens=[32, 7, 64])
+    Q = device_tokens(q, q_off, "f16")
+    D = device_tokens(d, d_off, "f16")
+    ref = M.score(Q, D).cpu().numpy()
+    rep = M.autotune(Q, D, reps=2)
+    assert len(rep["trials"]) >= 6 and rep["best"]["ms"] > 0
+    assert np.array_equal(M.score(Q, D).cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "fp8"])
+def test_unfused_comparator(dtype):
+    q, q_off, d, d_off = _ragged(500, 128, seed=41, nq_lens=[32, 12], empty_every=97)
+    Q = device_tokens(q, q_off, dtype)
+    D = device_tokens(d, d_off, dtype)
+    fused = M.score(Q, D).cpu().numpy()
+    unf = M.score_unfused(Q, D).cpu().numpy()
+    want = o1_scores(q, q_off, d, d_off, dtype)
+    assert_close_o1(unf, want, "unfused")
+    for a in range(2):
+        f = fused[a * 500:(a + 1) * 500]
+        u = unf[a * 500:(a + 1) * 500]
+        assert set(np.argsort(-f, kind="stable")[:100]) == set(np.argsort(-u, kind="stable")[:100])
+
+
+def test_query_capacity_is_enforced():
+    q, q_off, d, d_off = _ragged(10, 128, seed=2, nq_lens=[65])
+    with pytest.raises(M.MaxSimError):
+        M.score(device_tokens(q, q_off, "f16"), device_tokens(d, d_off, "f16"))
+    # a caller that understates max_len gets NaN scores, never an overrun
+    Q = device_tokens(q, q_off, "f16", max_len=32)
+    got = M.score(Q, device_tokens(d, d_off, "f16")).cpu().numpy()
+    assert np.all(np.isnan(got))
+
+
+# ----------------------------------------------------------------- top-k
+
+@pytest.mark.parametrize("k", [1, 7, 100])
+def test_topk_bit_exact(k):
+    sizes = [0, 5, 100, 1000, 3, 70000, 130]
+    off = W.offsets_from_lengths(sizes)
+    parts = [W.random_scores(s, seed=i, n_distinct=(None if i % 2 else 40))
+             for i, s in enumerate(sizes)]
+    s = np.concatenate(parts).astype(np.float32)
+    s[off[1] + 1] = -np.inf
+    s[off[1] + 3] = np.nan
+    ids = W.rng(3).permutation(len(s)).astype(np.int32)
+    for use_ids in (True, False):
+        gs, gi = M.topk(dev(s), dev(off), k, ids=dev(ids) if use_ids else None)
+        gs, gi = gs.cpu().numpy(), gi.cpu().numpy()
+        for a in range(len(sizes)):
+            seg = s[off[a]:off[a + 1]]
+            sid = ids[off[a]:off[a + 1]].astype(np.int64) if use_ids else np.arange(len(seg))
+            if np.isnan(seg).any():
+                # brute force: finite and -inf by (score desc, id asc), NaN last
+                order = sorted(range(len(seg)), key=lambda i: (bool(np.isnan(seg[i])),
+                               0.0 if np.isnan(seg[i]) else -float(seg[i]), int(sid[i])))[:k]
+                want_i = [int(sid[i]) for i in order] + [-1] * (k - len(order))
+                assert gi[a].tolist() == want_i, a
+                continue
+            wi, ws = oracle.topk(seg.astype(np.float64), k, sid if use_ids else None)
+            assert gi[a].tolist() == wi.tolist(), a
+            assert np.array_equal(gs[a].astype(np.float64), ws), a
+
+
+# ----------------------------------------------------------------- PQ
+
+def _pq_case(n_docs, M_, K, dsub, seed, nq_lens, integer=False):
+    g = W.rng(seed)
+    lens = W.doc_lengths(n_docs, seed)
+    lens[0] = 0
+    d_off = W.offsets_from_lengths(lens)
+    codes = g.integers(0, K, size=(int(d_off[-1]), M_), dtype=np.uint8)
+    q_off = W.offsets_from_lengths(nq_lens)
+    if integer:
+        cb = g.integers(-4, 5, size=(M_, K, dsub)).astype(np.float16)
+        q = g.integers(-3, 4, size=(int(q_off[-1]), M_ * dsub)).astype(np.float16)
+    else:
+        cb = (g.standard_normal((M_, K, dsub)) * 0.25).astype(np.float16)
+        q = W.unit_tokens(int(q_off[-1]), M_ * dsub, g).astype(np.float16)
+    return q, q_off, cb, codes, d_off
+
+
+def _pq_device(q, q_off, cb, codes, d_off):
+    Q = M.Tokens(dev(q), dev(q_off), "f16")
+    D = M.PQDocs(dev(cb), dev(codes), dev(d_off))
+    return Q, D
+
+
+def test_pq_integer_table_is_bit_exact():
+    q, q_off, cb, codes, d_off = _pq_case(200, 8, 256, 16, seed=1, nq_lens=[32, 5], integer=True)
+    Q, D = _pq_device(q, q_off, cb, codes, d_off)
+    got = M.pq_score(Q, D).cpu().numpy()
+    want = oracle.pq_decode_score(q.astype(np.float64), q_off, codes, cb.astype(np.float64), d_off)
+    assert np.array_equal(got.astype(np.float64), want)
+
+
+@pytest.mark.parametrize("shape", [(8, 256, 16), (16, 256, 8), (4, 64, 32)])
+def test_pq_matches_decode_then_score(shape):
+    M_, K, dsub = shape
+    q, q_off, cb, codes, d_off = _pq_case(300, M_, K, dsub, seed=M_ + K, nq_lens=[32, 64, 3])
+    Q, D = _pq_device(q, q_off, cb, codes, d_off)
+    got = M.pq_score(Q, D).cpu().numpy()
+    want = oracle.pq_decode_score(q.astype(np.float64), q_off, codes, cb.astype(np.float64), d_off)
+    assert_close_o1(got, want, f"pq {shape}")
+
+
+def test_pq_candidates():
+    q, q_off, cb, codes, d_off = _pq_case(500, 8, 256, 16, seed=7, nq_lens=[32, 16, 50])
+    cand_off, cand_ids = W.candidates(3, 500, seed=8, size_range=(50, 400))
+    Q, D = _pq_device(q, q_off, cb, codes, d_off)
+    got = M.pq_score(Q, D, M.Candidates(dev(cand_off), dev(cand_ids))).cpu().numpy()
+    want = oracle.pq_decode_score(q.astype(np.float64), q_off, codes, cb.astype(np.float64), d_off,
+                                  cand_off, cand_ids)
+    assert_close_o1(got, want, "pq candidates")
