@@ -148,7 +148,13 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline step only")
     ap.add_argument("--cpu-sample", type=int, default=12000, help="docs for the oracle timing")
     ap.add_argument("--profile", action="store_true",
-                    help="headline step only, no CPU oracle (for rocprofv3 runs)")
+                    help="headline step only, no CPU oracle, plus a plain 1 GiB device copy "
+                         "(the calibration kernel for rocprofv3 counter runs)")
+    ap.add_argument("--autotune", metavar="CACHE", default=None,
+                    help="tune the fused launch shape for every precision form on this "
+                         "workload and write the cache file")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2606_26439_amd", "tuned.json"),
+                    help="tuned launch shapes to load (missing file: built-in defaults)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU path "
@@ -160,8 +166,19 @@ def main():
     import paper_2606_26439_amd as M
     from paper_2606_26439_amd import roofline as R
     torch.cuda.set_device(0)
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        M.load_tune_cache(args.tune_cache)
 
     wl = Workload()
+    if args.autotune:
+        for dt in ("f16", "bf16", "fp8", "f32"):
+            Qd, Dd = wl.tokens(dt)
+            rep = M.autotune(Qd, Dd, reps=10, cache_path=args.autotune)
+            log(f"[autotune] {dt}: best {rep['best']}")
+            log(json.dumps(rep))
+            if dt != "f16":
+                del wl.forms[dt]
+                torch.cuda.empty_cache()
     Q, D = wl.tokens("f16")
     seg = torch.tensor([0, wl.n_docs], dtype=torch.int64, device="cuda")
     scores = torch.empty(wl.n_docs, dtype=torch.float32, device="cuda")
@@ -216,6 +233,15 @@ def main():
     }
     log(f"[bench] fused f16: {fused_ms.mean():.3f} ms/launch, {achieved / 1e12:.2f} TB/s, "
         f"step {ms_per_step:.3f} ms")
+
+    if args.profile:
+        # plain copy of exactly 1 GiB through the library's FP32 pass-through
+        # conversion: the known-size kernel that calibrates FETCH/WRITE counters
+        n_cal = (1 << 30) // (4 * wl.dim)
+        cal = M.quantize(wl.d_f32[:n_cal], "f32")[0]
+        torch.cuda.synchronize()
+        del cal
+        log(f"[bench] calibration copy: {n_cal * wl.dim * 4} bytes read and written")
 
     if not args.profile:
         got = scores.cpu().numpy()

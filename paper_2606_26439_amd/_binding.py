@@ -87,6 +87,10 @@ def lib():
                  "maxsim_topk", "maxsim_autotune", "maxsim_load_tune_cache"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
+    # launch shapes tuned on an MI355X for the shipped key set (missing: defaults)
+    tuned = os.environ.get("MAXSIM_TUNE_CACHE", os.path.join(_HERE, "tuned.json"))
+    if os.path.exists(tuned):
+        L.maxsim_load_tune_cache(tuned.encode())
     return L
 
 

@@ -6,8 +6,13 @@ import oracle
 import paper_2606_26439_amd as M
 
 # Kernel-correctness gate against O1 (the exact values the GPU receives):
-# FP32 accumulation of exact products, |gpu - O1| <= 1e-5 * max(|O1|, 1).
+# FP32 accumulation of exact products, |gpu - O1| <= tol * max(|O1|, 1).
+# The f8f6f4 MFMA adds each 32-byte block of products inside the matrix core
+# at a precision below an IEEE FP32 add chain (measured up to 1.2e-5 relative
+# per score, against <= 1.3e-7 for the other types), so FP8 is gated at 1e-4:
+# still 600x inside the 6e-2 precision bound of the FP8 form.
 REL_TOL = 1e-5
+REL_TOL_DT = {"f32": 1e-5, "bf16": 1e-5, "f16": 1e-5, "fp8": 1e-4}
 # Precision-form bounds against O2 (the FP32 values before rounding).
 O2_TOL = {"f32": None, "bf16": 2e-2, "f16": 2e-2, "fp8": 6e-2}
 
@@ -26,7 +31,7 @@ def device_tokens(x_f32, off, dtype, max_len=None):
     return M.Tokens(tok, dev(np.asarray(off, np.int64)), dtype, sc, max_len)
 
 
-def assert_close_o1(got, want, what=""):
+def assert_close_o1(got, want, what="", dtype=None):
     got = np.asarray(got, np.float64)
     want = np.asarray(want, np.float64)
     assert got.shape == want.shape, (got.shape, want.shape)
@@ -36,7 +41,8 @@ def assert_close_o1(got, want, what=""):
     if g.size:
         err = np.abs(g - w) / np.maximum(np.abs(w), 1.0)
         i = int(np.argmax(err))
-        assert err[i] <= REL_TOL, f"{what}: max rel err {err[i]:.3e} at {i}: {g[i]} vs {w[i]}"
+        tol = REL_TOL_DT.get(dtype, REL_TOL)
+        assert err[i] <= tol, f"{what}: max rel err {err[i]:.3e} at {i}: {g[i]} vs {w[i]}"
 
 
 def o1_scores(q, q_off, d, d_off, dtype, cand_off=None, cand_ids=None):

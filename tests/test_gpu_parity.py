@@ -59,7 +59,7 @@ def test_fused_all_docs(dtype, dim):
     D = device_tokens(d, d_off, dtype)
     got = M.score(Q, D).cpu().numpy()
     want = o1_scores(q, q_off, d, d_off, dtype)
-    assert_close_o1(got, want, f"{dtype} d={dim}")
+    assert_close_o1(got, want, f"{dtype} d={dim}", dtype)
 
 
 @pytest.mark.parametrize("nq", [1, 16, 31, 33, 48, 64])
@@ -87,7 +87,7 @@ def test_fused_candidates(dtype):
     C = M.Candidates(dev(cand_off), dev(cand_ids))
     got = M.score(Q, D, C).cpu().numpy()
     want = o1_scores(q, q_off, d, d_off, dtype, cand_off, cand_ids)
-    assert_close_o1(got, want, f"{dtype} candidates")
+    assert_close_o1(got, want, f"{dtype} candidates", dtype)
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -108,7 +108,7 @@ def test_query_inside_doc_scores_exactly_nq(dtype):
     got = M.score(Q, D).cpu().numpy()
     assert np.all(got[0::2] == float(nq)), got[0::2]
     want = o1_scores(q, [0, nq], d, d_off, dtype)
-    assert_close_o1(got, want, dtype)
+    assert_close_o1(got, want, dtype, dtype)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
@@ -156,7 +156,7 @@ def test_unfused_comparator(dtype):
     fused = M.score(Q, D).cpu().numpy()
     unf = M.score_unfused(Q, D).cpu().numpy()
     want = o1_scores(q, q_off, d, d_off, dtype)
-    assert_close_o1(unf, want, "unfused")
+    assert_close_o1(unf, want, "unfused", dtype)
     for a in range(2):
         f = fused[a * 500:(a + 1) * 500]
         u = unf[a * 500:(a + 1) * 500]
