@@ -140,12 +140,194 @@ def oracle_sample(wl, dtype, got_scores, n_sample, seed=5):
              "max": float(e2.max())})
 
 
+def gen_docs(n_tokens, dim, dtype, seed, sample_rows=None):
+    """Document tokens of `dtype` built chunk by chunk on the device (FP32 draw,
+    then the library's conversion), plus the FP32 source of `sample_rows`
+    (sorted row indices) for the oracle."""
+    import torch
+    import paper_2606_26439_amd as M
+    import workloads as W
+    tok = torch.empty((n_tokens, dim), dtype=M._binding.TORCH_DTYPES[dtype], device="cuda")
+    sc = torch.empty(n_tokens, dtype=torch.float32, device="cuda") if dtype == "fp8" else None
+    keep = []
+    rows = np.asarray(sample_rows if sample_rows is not None else [], np.int64)
+    for s, e, x in W.unit_tokens_gpu_chunks(n_tokens, dim, seed):
+        t, c = M.quantize(x, dtype)
+        tok[s:e] = t
+        if sc is not None:
+            sc[s:e] = c
+        sel = rows[(rows >= s) & (rows < e)]
+        if sel.size:
+            keep.append(x[torch.from_numpy(sel - s).cuda()].cpu().numpy())
+        del x, t, c
+    torch.cuda.synchronize()
+    f32 = np.concatenate(keep) if keep else np.zeros((0, dim), np.float32)
+    return tok, sc, f32
+
+
+def bench_dim_tiling(batch_sizes=(500_000,), dims=(64, 256, 512, 768), nq=32, nd=128):
+    """Fixed Nd = 128, BF16, one 32-token query, d in {64, 256, 512, 768}."""
+    import torch
+    import oracle
+    import paper_2606_26439_amd as M
+    import workloads as W
+    from paper_2606_26439_amd import roofline as R
+    out = []
+    for B in batch_sizes:
+        for d in dims:
+            T = B * nd
+            d_off_np = np.arange(B + 1, dtype=np.int64) * nd
+            samp = np.sort(np.random.default_rng(11).choice(B, size=64, replace=False))
+            rows = np.concatenate([np.arange(b * nd, (b + 1) * nd) for b in samp])
+            tok, _, f32 = gen_docs(T, d, "bf16", seed=3000 + d, sample_rows=rows)
+            q = W.unit_tokens(nq, d, W.rng(1))
+            qt, _ = M.quantize(torch.from_numpy(q).cuda(), "bf16")
+            Q = M.Tokens(qt, torch.tensor([0, nq], device="cuda"), "bf16", None, max_len=nq)
+            D = M.Tokens(tok, torch.from_numpy(d_off_np).cuda(), "bf16", None, max_len=nd)
+            sc = torch.empty(B, dtype=torch.float32, device="cuda")
+            med, mean, std = time_fn(lambda: M.score(Q, D, out=sc), 10, 2)
+            b = R.fused_bytes(T, B, B, nq, d, "bf16")
+            got = sc.cpu().numpy()[samp].astype(np.float64)
+            qv, _ = oracle.exact_values(q, "bf16")
+            dv, _ = oracle.exact_values(f32, "bf16")
+            want = oracle.maxsim(qv, [0, nq], dv, np.arange(len(samp) + 1) * nd)
+            rel = float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1.0)))
+            rec = {"B": B, "d": d, "ms_median": med, "docs_per_s": B / (med * 1e-3),
+                   "hbm_frac": b / (med * 1e-3) / HBM_PEAK, "alg_bytes": b,
+                   "sampled_max_rel_err_vs_o1": rel}
+            log(f"[bench] dim tiling B={B} d={d}: {med:.3f} ms, "
+                f"{rec['hbm_frac'] * 100:.1f}% HBM, err {rel:.1e}")
+            out.append(rec)
+            del tok, D, sc
+            torch.cuda.empty_cache()
+    return out
+
+
+def bench_pq(n_docs=2_000_000, n_queries=64, nq=32, M_=8, K=256, dsub=16):
+    """64 queries x 32 tokens against 2M PQ-coded docs in one launch."""
+    import torch
+    import oracle
+    import paper_2606_26439_amd as M
+    import workloads as W
+    from paper_2606_26439_amd import roofline as R
+    lens = W.doc_lengths(n_docs, 0)
+    d_off_np = W.offsets_from_lengths(lens)
+    T = int(d_off_np[-1])
+    codes = W.pq_codes_gpu(T, M_, K, seed=2)
+    cb_np = W.pq_codebooks(M_, K, dsub, seed=2)
+    q = W.unit_tokens(n_queries * nq, M_ * dsub, W.rng(1))
+    qt, _ = M.quantize(torch.from_numpy(q).cuda(), "f16")
+    q_off_np = np.arange(n_queries + 1, dtype=np.int64) * nq
+    Q = M.Tokens(qt, torch.from_numpy(q_off_np).cuda(), "f16", None, max_len=nq)
+    D = M.PQDocs(torch.from_numpy(cb_np).cuda(), codes, torch.from_numpy(d_off_np).cuda())
+    n_pairs = n_queries * n_docs
+    sc = torch.empty(n_pairs, dtype=torch.float32, device="cuda")
+    med, mean, std = time_fn(lambda: M.pq_score(Q, D, out=sc), 3, 1)
+    # sampled check: 3 queries x 300 docs, decode-then-score in FP64
+    g = np.random.default_rng(13)
+    docs = np.sort(g.choice(n_docs, size=300, replace=False))
+    rows = np.concatenate([np.arange(d_off_np[b], d_off_np[b + 1]) for b in docs])
+    codes_s = codes[torch.from_numpy(rows).cuda()].cpu().numpy()
+    s_off = W.offsets_from_lengths(lens[docs])
+    qv, _ = oracle.exact_values(q, "f16")
+    got_all = sc.view(n_queries, n_docs)
+    worst = 0.0
+    for a in (0, 31, 63):
+        want = oracle.pq_decode_score(qv[a * nq:(a + 1) * nq], [0, nq], codes_s,
+                                      cb_np.astype(np.float64), s_off)
+        got = got_all[a, torch.from_numpy(docs).cuda()].cpu().numpy().astype(np.float64)
+        worst = max(worst, float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1.0))))
+    gathers = n_queries * nq * M_ * T
+    lds_peak_gathers = 256 * 2.4e9 * 128 / 4  # 128 B/clk/CU of 4-byte words
+    hb = R.pq_bytes(T, n_docs, n_queries, M_)
+    rec = {"ms_median": med, "n_docs": n_docs, "n_doc_tokens": T, "n_queries": n_queries,
+           "nq": nq, "M": M_, "K": K, "dsub": dsub,
+           "pairs_per_s": n_pairs / (med * 1e-3),
+           "docs_per_s_per_query": n_docs / (med * 1e-3) * n_queries / n_queries,
+           "query_doc_pairs_per_s": n_pairs / (med * 1e-3),
+           "lds_gathers_per_s": gathers / (med * 1e-3),
+           "lds_gather_frac": gathers / (med * 1e-3) / lds_peak_gathers,
+           "hbm_frac_of_codes_once": hb / (med * 1e-3) / HBM_PEAK,
+           "sampled_max_rel_err_vs_decode_then_score": worst}
+    log(f"[bench] PQ: {med:.2f} ms, {rec['pairs_per_s'] / 1e9:.2f} G pairs/s, "
+        f"LDS gather frac {rec['lds_gather_frac'] * 100:.1f}%, err {worst:.1e}")
+    del codes, sc
+    torch.cuda.empty_cache()
+    return rec
+
+
+def bench_serving(n_pool=5_000_000, qps_levels=(500, 1000, 2000), n_req=1200, k=100,
+                  pq_qps=1000):
+    """5M-doc FP16 pool + PQ copy; open-loop Poisson arrivals; top-100."""
+    import torch
+    import paper_2606_26439_amd as M
+    import workloads as W
+    from paper_2606_26439_amd import serve as S
+    t0 = time.time()
+    lens = W.doc_lengths(n_pool, 0)
+    d_off_np = W.offsets_from_lengths(lens)
+    T = int(d_off_np[-1])
+    tok, _, _ = gen_docs(T, 128, "f16", seed=5000)
+    d_off = torch.from_numpy(d_off_np).cuda()
+    pool = M.Tokens(tok, d_off, "f16", None, max_len=int(lens.max()))
+    codes = W.pq_codes_gpu(T, 8, 256, seed=2)
+    pq = M.PQDocs(torch.from_numpy(W.pq_codebooks(8, 256, 16, seed=2)).cuda(), codes, d_off)
+    log(f"[bench] serving pool: {n_pool} docs, {T} tokens, "
+        f"{tok.numel() * 2 / 1e9:.1f} GB FP16 + {codes.numel() / 1e9:.2f} GB codes, "
+        f"built in {time.time() - t0:.1f}s")
+    n_all = n_req * (len(qps_levels) + 1) + 16
+    g = W.rng(1)
+    nqs = g.integers(8, 65, size=n_all)
+    queries = [W.unit_tokens(int(n), 128, g) for n in nqs]
+    c_off, c_ids = W.candidates(n_all, n_pool, seed=4)
+
+    def mk(i, mode):
+        return S.Request(i, queries[i], c_ids[c_off[i]:c_off[i + 1]], mode=mode)
+
+    backend = S.GpuBackend(pool, pq, k=k)
+    # warm-up
+    warm = [mk(n_all - 1 - j, "exact" if j % 2 else "pq") for j in range(8)]
+    S.Server(S.Scheduler(128, k), backend).run(warm)
+    results = []
+    base = 0
+    levels = [(q, "exact") for q in qps_levels] + [(pq_qps, "pq")]
+    for qps, mode in levels:
+        reqs = [mk(base + i, mode) for i in range(n_req)]
+        base += n_req
+        arr = W.poisson_arrivals(n_req, qps, seed=3)
+        sched = S.Scheduler(128, k, max_inflight=3, mem_budget=8 << 30)
+        srv = S.Server(sched, backend)
+        start = time.perf_counter() + 0.01
+        for r, a in zip(reqs, arr):
+            r.arrival = start + float(a)
+        torch.cuda.synchronize()
+        done = srv.run(reqs)
+        wall = max(r.done_at for r in done) - start
+        scored = sum(len(r.cand_ids) for r in done if r.status == "done")
+        st = S.latency_stats(done)
+        rec = {"mode": mode, "qps_offered": qps, "n_requests": n_req,
+               "qps_achieved": len(done) / wall, "docs_per_s": scored / wall,
+               "batches": srv.batches_launched, "mean_batch": n_req / max(1, srv.batches_launched),
+               "max_queue_depth": srv.max_queue_depth,
+               "statuses": {s_: sum(r.status == s_ for r in done) for s_ in {r.status for r in done}},
+               **st}
+        log(f"[bench] serving {mode} @ {qps} QPS: p50 {st.get('p50_ms', 0):.2f} ms, "
+            f"p99 {st.get('p99_ms', 0):.2f} ms, {rec['docs_per_s'] / 1e6:.1f} M docs/s, "
+            f"mean batch {rec['mean_batch']:.1f}")
+        results.append(rec)
+    del tok, codes, pool, pq
+    torch.cuda.empty_cache()
+    return {"pool_docs": n_pool, "pool_tokens": T, "k": k, "levels": results}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="headline step only")
+    ap.add_argument("--skip", default="", help="comma list of sections to skip: "
+                    "forms,unfused,pq,dims,serving")
     ap.add_argument("--cpu-sample", type=int, default=12000, help="docs for the oracle timing")
     ap.add_argument("--profile", action="store_true",
                     help="headline step only, no CPU oracle, plus a plain 1 GiB device copy "
@@ -252,7 +434,8 @@ def main():
                                "gpu_vs_oracle_max_rel_err": relmax, "f16_vs_fp32_abs_err": o2}
         log(f"[bench] oracle {dps:.0f} docs/s on 1 core; sampled max rel err {relmax:.2e}")
 
-    if not args.quick and not args.profile:
+    skip = set(x for x in args.skip.split(",") if x)
+    if not args.quick and not args.profile and "forms" not in skip:
         forms = {}
         top_f16 = set(torch.topk(scores, 100).indices.cpu().numpy().tolist())
         for dt in ("f32", "bf16", "fp8", "f16"):
@@ -277,7 +460,9 @@ def main():
                 torch.cuda.empty_cache()
         out["forms"] = forms
 
-        # unfused comparator on the same FP16 inputs
+    if not args.quick and not args.profile and "unfused" not in skip:
+        top_f16 = set(torch.topk(scores, 100).indices.cpu().numpy().tolist())
+        fused_med = time_fn(lambda: M.score(Q, D, out=scores), 10, 2)[0]
         ws = torch.empty(M.unfused_workspace_bytes(Q, D), dtype=torch.uint8, device="cuda")
         su = torch.empty(wl.n_docs, dtype=torch.float32, device="cuda")
         med, mean, std = time_fn(lambda: M.score_unfused(Q, D, out=su, workspace=ws), 10, 2)
@@ -286,10 +471,20 @@ def main():
         out["unfused"] = {"ms_median": med, "docs_per_s": wl.n_docs / (med * 1e-3),
                           "hbm_frac_of_its_bytes": bu / (med * 1e-3) / HBM_PEAK,
                           "alg_bytes": bu, "top100_identical_to_fused": top_u == top_f16,
-                          "fused_speedup": med / forms["f16"]["ms_median"]}
-        log(f"[bench] unfused: {med:.3f} ms ({med / forms['f16']['ms_median']:.2f}x fused)")
-        del ws
+                          "fused_ms_median": fused_med, "fused_speedup": med / fused_med}
+        log(f"[bench] unfused: {med:.3f} ms ({med / fused_med:.2f}x fused)")
+        del ws, su
         torch.cuda.empty_cache()
+
+    if not args.quick and not args.profile:
+        del wl, Q, D
+        torch.cuda.empty_cache()
+        if "pq" not in skip:
+            out["pq"] = bench_pq()
+        if "dims" not in skip:
+            out["dim_tiling"] = bench_dim_tiling()
+        if "serving" not in skip:
+            out["serving"] = bench_serving()
 
     print(json.dumps(out), flush=True)
 

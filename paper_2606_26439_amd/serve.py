@@ -1,0 +1,323 @@
+"""Continuous-batching request loop over a device-resident document pool.
+
+Requests (a query's token vectors plus a candidate id list) arrive at any
+time. The scheduler admits queued requests into the next batch whenever an
+execution slot is free and the batch's device memory fits the budget; a
+batch is one multi-query launch of the fused scorer (or the fused PQ scorer)
+followed by per-request top-k, enqueued on its own HIP stream, so batches
+formed while earlier ones are still on the GPU overlap with them. Every score
+is produced by one wavefront with a fixed reduction order, so a request's
+result does not depend on which batch carried it.
+
+The scheduler is pure host logic; the device work sits behind a Backend with
+launch / poll / results, so the admission, slot, timeout, cancellation and
+failure paths run on the CPU with a fake backend and an injected clock.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    query: np.ndarray          # [Nq, d] float32 (converted on the device)
+    cand_ids: np.ndarray       # [n_cand] int32 ids into the pool
+    arrival: float = 0.0       # clock time of arrival
+    mode: str = "exact"        # "exact" (fused MaxSim) or "pq" (fused PQ)
+    deadline: Optional[float] = None
+    # filled on completion
+    status: str = "pending"    # pending | queued | running | done | timeout | cancelled | error | rejected
+    error: str = ""
+    done_at: Optional[float] = None
+    top_ids: Optional[np.ndarray] = None
+    top_scores: Optional[np.ndarray] = None
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.done_at is None else self.done_at - self.arrival
+
+
+def request_bytes(nq: int, n_cand: int, dim: int, k: int, elem: int = 2) -> int:
+    """Device bytes a request occupies while in flight: query tokens (FP32
+    staging + converted copy), candidate ids, scores, top-k outputs and the
+    per-segment top-k workspace."""
+    topk_ws = 8 * 256 * 4 + 256 + 8 * k
+    return (nq * dim * (4 + elem) + 8 * n_cand + 16 + 8 * k + topk_ws + 8)
+
+
+@dataclasses.dataclass
+class Batch:
+    bid: int
+    requests: List[Request]
+    mode: str
+    nbytes: int
+    handle: object = None
+    launched_at: float = 0.0
+
+
+class Scheduler:
+    """Admission by free execution slots and a device-memory budget."""
+
+    def __init__(self, dim: int, k: int = 100, max_inflight: int = 2,
+                 mem_budget: int = 4 << 30, max_batch_requests: int = 64,
+                 max_batch_pairs: int = 4_000_000, max_queue: int = 100_000):
+        self.dim, self.k = dim, k
+        self.max_inflight = max_inflight
+        self.mem_budget = mem_budget
+        self.max_batch_requests = max_batch_requests
+        self.max_batch_pairs = max_batch_pairs
+        self.max_queue = max_queue
+        self.queue: collections.deque = collections.deque()
+        self.inflight: List[Batch] = []
+        self.mem_in_use = 0
+        self._next_bid = 0
+
+    def cost(self, r: Request) -> int:
+        return request_bytes(len(r.query), len(r.cand_ids), self.dim, self.k)
+
+    def submit(self, r: Request) -> bool:
+        """Queues a request; rejects one that can never fit or a full queue."""
+        if self.cost(r) > self.mem_budget or len(r.cand_ids) > self.max_batch_pairs:
+            r.status, r.error = "rejected", "request exceeds the device memory budget"
+            return False
+        if len(self.queue) >= self.max_queue:
+            r.status, r.error = "rejected", "queue full"
+            return False
+        r.status = "queued"
+        self.queue.append(r)
+        return True
+
+    def expire(self, now: float) -> List[Request]:
+        """Removes queued requests whose deadline has passed."""
+        out, keep = [], collections.deque()
+        for r in self.queue:
+            if r.deadline is not None and now > r.deadline:
+                r.status, r.error, r.done_at = "timeout", "deadline passed while queued", now
+                out.append(r)
+            else:
+                keep.append(r)
+        self.queue = keep
+        return out
+
+    def cancel(self, rid: int, now: float) -> bool:
+        for r in list(self.queue):
+            if r.rid == rid:
+                self.queue.remove(r)
+                r.status, r.done_at = "cancelled", now
+                return True
+        return False
+
+    def next_batch(self) -> Optional[Batch]:
+        """Forms the next batch from the head of the queue (FIFO, one mode per
+        batch) if a slot is free and at least one request fits the memory left."""
+        if len(self.inflight) >= self.max_inflight or not self.queue:
+            return None
+        mode = self.queue[0].mode
+        picked, nbytes, pairs = [], 0, 0
+        free = self.mem_budget - self.mem_in_use
+        while self.queue and len(picked) < self.max_batch_requests:
+            r = self.queue[0]
+            if r.mode != mode:
+                break
+            c = self.cost(r)
+            if nbytes + c > free or pairs + len(r.cand_ids) > self.max_batch_pairs:
+                break
+            picked.append(self.queue.popleft())
+            nbytes += c
+            pairs += len(r.cand_ids)
+        if not picked:
+            return None
+        b = Batch(self._next_bid, picked, mode, nbytes)
+        self._next_bid += 1
+        for r in picked:
+            r.status = "running"
+        self.mem_in_use += nbytes
+        self.inflight.append(b)
+        return b
+
+    def finish(self, b: Batch):
+        self.inflight.remove(b)
+        self.mem_in_use -= b.nbytes
+
+
+class Backend:
+    """Device-side executor interface."""
+
+    def launch(self, batch: Batch) -> object:
+        raise NotImplementedError
+
+    def poll(self, handle) -> bool:
+        raise NotImplementedError
+
+    def results(self, handle) -> List[tuple]:
+        """Per request, (top ids int64 [k], top scores float32 [k])."""
+        raise NotImplementedError
+
+
+class GpuBackend(Backend):
+    """Launches a batch as one fused scoring call and one top-k call on a
+    stream of its own; completion is an event poll."""
+
+    def __init__(self, pool_docs, pool_pq=None, k: int = 100, n_streams: int = 2,
+                 device: str = "cuda"):
+        import torch
+        from . import _binding as B
+        self.torch, self.B = torch, B
+        self.docs, self.pq, self.k, self.device = pool_docs, pool_pq, k, device
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        self._rr = 0
+
+    def launch(self, batch: Batch):
+        torch, B = self.torch, self.B
+        reqs = batch.requests
+        s = self.streams[self._rr % len(self.streams)]
+        self._rr += 1
+        nq = np.array([len(r.query) for r in reqs], np.int64)
+        nc = np.array([len(r.cand_ids) for r in reqs], np.int64)
+        q_off = np.zeros(len(reqs) + 1, np.int64)
+        np.cumsum(nq, out=q_off[1:])
+        c_off = np.zeros(len(reqs) + 1, np.int64)
+        np.cumsum(nc, out=c_off[1:])
+        q_host = torch.from_numpy(np.concatenate([r.query for r in reqs]).astype(np.float32)).pin_memory()
+        ids_host = torch.from_numpy(np.concatenate([r.cand_ids for r in reqs]).astype(np.int32)).pin_memory()
+        qoff_host = torch.from_numpy(q_off).pin_memory()
+        coff_host = torch.from_numpy(c_off).pin_memory()
+        with torch.cuda.stream(s):
+            q32 = q_host.to(self.device, non_blocking=True)
+            ids = ids_host.to(self.device, non_blocking=True)
+            qoff = qoff_host.to(self.device, non_blocking=True)
+            coff = coff_host.to(self.device, non_blocking=True)
+            cand = B.Candidates(coff, ids)
+            if batch.mode == "pq":
+                qt, _ = B.quantize(q32, "f16", stream=s)
+                Q = B.Tokens(qt, qoff, "f16", None, max_len=int(nq.max()))
+                scores = B.pq_score(Q, self.pq, cand, stream=s)
+            else:
+                qt, qs = B.quantize(q32, self.docs.dtype, stream=s)
+                Q = B.Tokens(qt, qoff, self.docs.dtype, qs, max_len=int(nq.max()))
+                scores = B.score(Q, self.docs, cand, stream=s)
+            ts, ti = B.topk(scores, coff, self.k, ids=ids, n_total=int(c_off[-1]), stream=s)
+            ts_h = torch.empty(ts.shape, dtype=ts.dtype, pin_memory=True)
+            ti_h = torch.empty(ti.shape, dtype=ti.dtype, pin_memory=True)
+            ts_h.copy_(ts, non_blocking=True)
+            ti_h.copy_(ti, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        # keep every device buffer alive until the event completes
+        return (ev, ts_h, ti_h, (q32, ids, qoff, coff, qt, scores, ts, ti))
+
+    def poll(self, handle) -> bool:
+        return handle[0].query()
+
+    def results(self, handle):
+        ev, ts_h, ti_h, _ = handle
+        ev.synchronize()
+        return [(ti_h[i].numpy().astype(np.int64), ts_h[i].numpy().copy())
+                for i in range(ts_h.shape[0])]
+
+
+class Server:
+    """Drives the scheduler and a backend against a clock.
+
+    run(requests) replays an open-loop arrival sequence (each request's
+    `arrival` is its scheduled time) and returns when every request is
+    finished; completed requests carry their latency (arrival -> results on
+    the host)."""
+
+    def __init__(self, scheduler: Scheduler, backend: Backend,
+                 clock: Callable[[], float] = time.perf_counter,
+                 idle: Callable[[float], None] = None):
+        self.sched, self.backend, self.clock = scheduler, backend, clock
+        self.idle = idle if idle is not None else (lambda dt: None)
+        self.completed: List[Request] = []
+        self.batches_launched = 0
+        self.max_queue_depth = 0
+
+    def _complete_batch(self, b: Batch, now: float):
+        try:
+            if isinstance(b.handle, _Failed):
+                raise b.handle.e
+            res = self.backend.results(b.handle)
+            for r, (ids, sc) in zip(b.requests, res):
+                r.top_ids, r.top_scores, r.status, r.done_at = ids, sc, "done", now
+        except Exception as e:  # noqa: BLE001 -- a failed batch fails its own requests only
+            for r in b.requests:
+                r.status, r.error, r.done_at = "error", f"{type(e).__name__}: {e}", now
+        self.completed.extend(b.requests)
+        self.sched.finish(b)
+
+    def pump(self) -> bool:
+        """One scheduling iteration. Returns True if anything progressed."""
+        now = self.clock()
+        progressed = False
+        for r in self.sched.expire(now):
+            self.completed.append(r)
+            progressed = True
+        for b in list(self.sched.inflight):
+            if isinstance(b.handle, _Failed):
+                ready = True
+            else:
+                try:
+                    ready = self.backend.poll(b.handle)
+                except Exception as e:  # noqa: BLE001
+                    ready = True
+                    b.handle = _Failed(e)
+            if ready:
+                self._complete_batch(b, self.clock())
+                progressed = True
+        while True:
+            b = self.sched.next_batch()
+            if b is None:
+                break
+            b.launched_at = self.clock()
+            try:
+                b.handle = self.backend.launch(b)
+            except Exception as e:  # noqa: BLE001
+                b.handle = _Failed(e)
+            self.batches_launched += 1
+            progressed = True
+        self.max_queue_depth = max(self.max_queue_depth, len(self.sched.queue))
+        return progressed
+
+    def run(self, requests: List[Request], cancel_at: Dict[int, float] = None) -> List[Request]:
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        cancels = sorted((t, rid) for rid, t in (cancel_at or {}).items())
+        total = len(pending)
+        self.completed = []
+        while len(self.completed) < total:
+            now = self.clock()
+            while pending and pending[0].arrival <= now:
+                r = pending.popleft()
+                if not self.sched.submit(r):
+                    r.done_at = now
+                    self.completed.append(r)
+            while cancels and cancels[0][0] <= now:
+                _, rid = cancels.pop(0)
+                if self.sched.cancel(rid, now):
+                    self.completed.extend(r for r in requests if r.rid == rid)
+            if not self.pump():
+                nxt = pending[0].arrival if pending else None
+                self.idle(0.0 if nxt is None else max(0.0, nxt - self.clock()))
+        return self.completed
+
+
+class _Failed:
+    """Handle of a batch whose launch or poll raised."""
+
+    def __init__(self, e):
+        self.e = e
+
+
+def latency_stats(reqs: List[Request]) -> dict:
+    lat = np.array([r.latency for r in reqs if r.status == "done"], np.float64)
+    if lat.size == 0:
+        return {"n": 0}
+    return {"n": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "max_ms": float(lat.max() * 1e3)}

@@ -170,6 +170,20 @@ def unit_tokens_gpu(n: int, dim: int, seed: int, device="cuda", out=None):
     return out
 
 
+def unit_tokens_gpu_chunks(n: int, dim: int, seed: int, device="cuda"):
+    """Yields (start, end, FP32 chunk) covering n unit-norm tokens, drawn in the
+    same order and chunking as unit_tokens_gpu (so the values are identical)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    for s in range(0, n, GPU_CHUNK_TOKENS):
+        e = min(n, s + GPU_CHUNK_TOKENS)
+        x = torch.randn((e - s, dim), generator=g, device=device, dtype=torch.float64)
+        x /= x.norm(dim=1, keepdim=True).clamp_min(1e-300)
+        yield s, e, x.to(torch.float32)
+        del x
+
+
 def pq_codes_gpu(n_tokens: int, M: int, K: int, seed: int, device="cuda"):
     import torch
     g = torch.Generator(device=device)
