@@ -326,6 +326,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="headline step only")
+    ap.add_argument("--only", choices=["pq", "dims", "serving"], default=None,
+                    help="run one secondary section alone and print its JSON")
     ap.add_argument("--skip", default="", help="comma list of sections to skip: "
                     "forms,unfused,pq,dims,serving")
     ap.add_argument("--cpu-sample", type=int, default=12000, help="docs for the oracle timing")
@@ -350,6 +352,11 @@ def main():
     torch.cuda.set_device(0)
     if args.tune_cache and os.path.exists(args.tune_cache):
         M.load_tune_cache(args.tune_cache)
+
+    if args.only:
+        fn = {"pq": bench_pq, "dims": bench_dim_tiling, "serving": bench_serving}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
+        return
 
     wl = Workload()
     if args.autotune:

@@ -104,7 +104,7 @@ typedef struct {
  * PQ-compressed documents (Sec. 4.1): token t is the concatenation over
  * m < M of centroid codebooks[m, codes[t, m], :] (dsub values each), so
  * dim = M * dsub.
- *   M in {4, 8, 16}; K <= 256; dsub a multiple of 4 with M * dsub <= 256.
+ *   M in {4, 8, 16}; 1 <= K <= 256; 1 <= dsub <= 32.
  *   cb_dtype MAXSIM_F16 or MAXSIM_F32 for codebooks[M, K, dsub].
  *   codes [n_tokens, M] uint8; offsets [n_docs + 1] int64 as for maxsim_csr.
  */

@@ -62,7 +62,7 @@ struct PqParams {
   int32_t qt;        // query tokens per slice (LUT rows)
   int32_t n_slices;  // ceil(max Nq / qt)
   int32_t n_chunks;  // doc-range chunks per (query, slice)
-  int32_t pad;
+  int32_t nw;        // waves per workgroup (8 or 16)
 };
 hipError_t launch_pq(const PqParams& P, int max_nq, hipStream_t s);
 
