@@ -211,6 +211,22 @@ maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
 /* Loads tuned configurations written by maxsim_autotune (missing file: OK, no-op). */
 maxsim_status maxsim_load_tune_cache(const char* cache_path);
 
+/*
+ * Measured HBM read ceiling (for reporting the scorers against what the
+ * device sustains as well as against its published peak; the paper reports
+ * utilisation against the published peak, Evaluation "Memory Bandwidth
+ * Utilization"). Streams `bytes` of buf (16-byte aligned; whole 4 KiB tiles
+ * are read) with 16-byte loads, one contiguous share per wave, and writes one
+ * XOR checksum per wave to sink (sink_len >= 4 entries; the grid is
+ * min(sink_len / 4, 8 * CUs) workgroups of 4 waves).
+ *   variant 0: lane-contiguous loads; 1: the same, non-temporal;
+ *           2: the fused scorer's 16-row tile pattern; 3: the same,
+ *           non-temporal; 4: lane-contiguous non-temporal loads straight
+ *           into LDS, read back from LDS.
+ */
+maxsim_status maxsim_stream_probe(const void* buf, size_t bytes, int32_t variant, uint32_t* sink,
+                                  int64_t sink_len, maxsim_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

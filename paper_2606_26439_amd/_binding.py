@@ -83,15 +83,24 @@ def lib():
                                   ctypes.c_int32, ctypes.c_char_p, ctypes.c_char_p,
                                   ctypes.c_size_t]
     L.maxsim_load_tune_cache.argtypes = [ctypes.c_char_p]
+    L.maxsim_stream_probe.argtypes = [_vp, ctypes.c_size_t, ctypes.c_int32, _vp, ctypes.c_int64,
+                                      _vp]
     for name in ("maxsim_quantize", "maxsim_score", "maxsim_score_unfused", "maxsim_pq_score",
-                 "maxsim_topk", "maxsim_autotune", "maxsim_load_tune_cache"):
+                 "maxsim_topk", "maxsim_autotune", "maxsim_load_tune_cache",
+                 "maxsim_stream_probe"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     # launch shapes tuned on an MI355X for the shipped key set (missing: defaults)
-    tuned = os.environ.get("MAXSIM_TUNE_CACHE", os.path.join(_HERE, "tuned.json"))
+    tuned = default_tune_cache()
     if os.path.exists(tuned):
         L.maxsim_load_tune_cache(tuned.encode())
     return L
+
+
+def default_tune_cache() -> str:
+    """The tune cache loaded with the library: $MAXSIM_TUNE_CACHE, else the
+    packaged tuned.json."""
+    return os.environ.get("MAXSIM_TUNE_CACHE", os.path.join(_HERE, "tuned.json"))
 
 
 def _check(st: int):
@@ -259,6 +268,15 @@ def autotune(q: Tokens, d: Tokens, cand: Candidates = None, reps: int = 10,
                                  _stream(stream), reps,
                                  cache_path.encode() if cache_path else None, buf, len(buf)))
     return json.loads(buf.value.decode())
+
+
+def stream_probe(buf, variant: int = 0, stream=None):
+    """Streams the bytes of `buf` (a device tensor) once; returns the checksum
+    tensor (one per wave). Time it with events to get the read ceiling."""
+    sink = torch.empty(256 * 8 * 4, dtype=torch.int32, device=buf.device)
+    _check(lib().maxsim_stream_probe(_ptr(buf), buf.numel() * buf.element_size(), variant,
+                                     _ptr(sink), sink.numel(), _stream(stream)))
+    return sink
 
 
 def load_tune_cache(path: str):

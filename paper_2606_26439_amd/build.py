@@ -27,6 +27,7 @@ SOURCES = [("fused_inst.hip", f"fused_dt{t}", [f"-DFUSED_DT={t}"]) for t in rang
     ("pq.hip", "pq", ["-fno-honor-nans"]),
     ("topk.hip", "topk", []),
     ("quantize.hip", "quantize", []),
+    ("probe.hip", "probe", []),
     ("api.cpp", "api", []),
 ]
 

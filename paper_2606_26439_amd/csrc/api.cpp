@@ -101,23 +101,40 @@ struct FusedCfg {
   int pf = 4;
   int nw = 4;
   int wg_per_cu = 0;  // 0: as many as fit
+  int stage = 0;      // 1: document tiles staged through LDS
 };
 
 std::mutex g_tune_mu;
 std::map<TuneKey, FusedCfg> g_tuned;
 
-FusedCfg default_cfg(int dt) {
+// Untuned keys: document tiles staged through LDS (the faster form measured on
+// MI355X for every element type but FP32) when the ring fits beside the query
+// block, else register-direct.
+FusedCfg default_cfg(int dt, size_t q_lds, int dch) {
   FusedCfg c;
-  c.pf = dt == MAXSIM_F32 ? 2 : 4;
   c.nw = 4;
   c.wg_per_cu = 0;
+  if (dt == MAXSIM_F32) {
+    c.pf = 2;
+    c.stage = 0;
+    return c;
+  }
+  c.pf = 3;
+  c.stage = 1;
+  if (q_lds + (size_t)c.nw * c.pf * 16 * dch * esize(dt) > device_info().max_lds) {
+    c.pf = 4;
+    c.stage = 0;
+  }
   return c;
 }
 
-FusedCfg lookup_cfg(const TuneKey& k) {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tuned.find(k);
-  return it == g_tuned.end() ? default_cfg(k.dt) : it->second;
+FusedCfg lookup_cfg(const TuneKey& k, size_t q_lds, int dch) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(k);
+    if (it != g_tuned.end()) return it->second;
+  }
+  return default_cfg(k.dt, q_lds, dch);
 }
 
 // ------------------------------------------------------------ fused plan --
@@ -180,16 +197,19 @@ maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_
 
 maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s) {
   if (pl.n_pairs == 0) return MAXSIM_OK;
-  FusedFns fns = fused_kernel_fns(pl.dt, pl.nqb, pl.dch, cfg.pf, cfg.nw, pl.qreg);
+  FusedFns fns = fused_kernel_fns(pl.dt, pl.nqb, pl.dch, cfg.pf, cfg.nw, pl.qreg, cfg.stage != 0);
   DevInfo di = device_info();
-  int occ = fns.occupancy(pl.lds);
+  size_t lds = pl.lds;
+  if (cfg.stage) lds += (size_t)cfg.nw * cfg.pf * 16 * pl.dch * esize(pl.dt);
+  if (lds > di.max_lds) return fail(MAXSIM_EUNSUPPORTED, "staged tiles need %zu bytes of LDS", lds);
+  int occ = fns.occupancy(lds);
   if (occ <= 0) return fail(MAXSIM_EHIP, "fused kernel does not fit on a compute unit");
   int per_cu = cfg.wg_per_cu > 0 ? std::min(cfg.wg_per_cu, occ) : occ;
   int64_t grid = (int64_t)per_cu * di.cus;
   int64_t need = (pl.n_pairs + cfg.nw - 1) / cfg.nw;  // at least one pair per wave
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
-  hipError_t e = fns.launch(pl.P, (int)grid, pl.lds, s);
+  hipError_t e = fns.launch(pl.P, (int)grid, lds, s);
   if (e != hipSuccess) return hip_fail(e, "fused MaxSim launch");
   return MAXSIM_OK;
 }
@@ -200,10 +220,12 @@ std::string cfg_json_all() {
   std::string out = "{\"version\":1,\"entries\":[";
   bool first = true;
   for (auto& kv : g_tuned) {
-    char b[160];
-    snprintf(b, sizeof b, "%s{\"dtype\":%d,\"dim\":%d,\"nqb\":%d,\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d}",
+    char b[192];
+    snprintf(b, sizeof b,
+             "%s{\"dtype\":%d,\"dim\":%d,\"nqb\":%d,\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d,"
+             "\"stage\":%d}",
              first ? "" : ",", kv.first.dt, kv.first.dim, kv.first.nqb, kv.second.pf, kv.second.nw,
-             kv.second.wg_per_cu);
+             kv.second.wg_per_cu, kv.second.stage);
     out += b;
     first = false;
   }
@@ -261,7 +283,7 @@ maxsim_status maxsim_score(const maxsim_csr* queries, const maxsim_csr* docs,
   FusedPlan pl;
   maxsim_status st = plan_fused(queries, docs, cand, scores, pl);
   if (st) return st;
-  FusedCfg cfg = lookup_cfg({pl.dt, queries->dim, pl.nqb});
+  FusedCfg cfg = lookup_cfg({pl.dt, queries->dim, pl.nqb}, pl.lds, pl.dch);
   return run_fused(pl, cfg, (hipStream_t)stream);
 }
 
@@ -426,6 +448,20 @@ maxsim_status maxsim_topk(const float* scores, const int64_t* seg_offsets, int64
   return MAXSIM_OK;
 }
 
+// ------------------------------------------------------- read ceiling --
+
+maxsim_status maxsim_stream_probe(const void* buf, size_t bytes, int32_t variant, uint32_t* sink,
+                                  int64_t sink_len, maxsim_stream_t stream) {
+  if (!buf || !sink) return fail(MAXSIM_EINVAL, "stream_probe: NULL buffer");
+  if (!aligned(buf, 16)) return fail(MAXSIM_EINVAL, "stream_probe: buffer must be 16-byte aligned");
+  if (variant < 0 || variant > 4) return fail(MAXSIM_EINVAL, "stream_probe: variant must be in [0, 4]");
+  if (sink_len < 4) return fail(MAXSIM_EINVAL, "stream_probe: sink needs at least 4 entries");
+  int64_t grid = std::min<int64_t>(sink_len / 4, (int64_t)device_info().cus * 8);
+  hipError_t e = launch_stream_probe(buf, bytes, variant, sink, (int)grid, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream_probe launch");
+  return MAXSIM_OK;
+}
+
 // ------------------------------------------------------------ autotune --
 
 maxsim_status maxsim_load_tune_cache(const char* path) {
@@ -448,7 +484,9 @@ maxsim_status maxsim_load_tune_cache(const char* path) {
     if (json_int(obj.c_str(), "dtype", k.dt) && json_int(obj.c_str(), "dim", k.dim) &&
         json_int(obj.c_str(), "nqb", k.nqb) && json_int(obj.c_str(), "pf", c.pf) &&
         json_int(obj.c_str(), "nw", c.nw) && json_int(obj.c_str(), "wg_per_cu", c.wg_per_cu)) {
-      if ((c.pf >= 2 && c.pf <= 4) && (c.nw == 4 || c.nw == 8)) g_tuned[k] = c;
+      if (!json_int(obj.c_str(), "stage", c.stage)) c.stage = 0;  // older caches
+      if ((c.pf >= 2 && c.pf <= 4) && (c.nw == 4 || c.nw == 8) && (c.stage == 0 || c.stage == 1))
+        g_tuned[k] = c;
     }
     pos = end;
   }
@@ -470,20 +508,22 @@ maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(MAXSIM_EHIP, "autotune: event creation failed");
   std::vector<FusedCfg> space;
-  for (int pf : {2, 3, 4})
-    for (int nw : {4, 8})
-      for (int wpc : {0, 1, 2}) {
-        FusedCfg c;
-        c.pf = pf;
-        c.nw = nw;
-        c.wg_per_cu = wpc;
-        space.push_back(c);
-      }
+  for (int stage : {0, 1})
+    for (int pf : {2, 3, 4})
+      for (int nw : {4, 8})
+        for (int wpc : {0, 1, 2}) {
+          FusedCfg c;
+          c.pf = pf;
+          c.nw = nw;
+          c.wg_per_cu = wpc;
+          c.stage = stage;
+          space.push_back(c);
+        }
   std::string rep = "{\"dtype\":" + std::to_string(pl.dt) + ",\"dim\":" +
                     std::to_string(queries->dim) + ",\"nqb\":" + std::to_string(pl.nqb) +
                     ",\"trials\":[";
   float best_ms = 1e30f;
-  FusedCfg best = default_cfg(pl.dt);
+  FusedCfg best = default_cfg(pl.dt, pl.lds, pl.dch);
   bool first = true;
   for (const FusedCfg& c : space) {
     if (run_fused(pl, c, s)) continue;  // warm-up (also skips shapes that do not fit)
@@ -496,8 +536,8 @@ maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
     (void)hipEventElapsedTime(&ms, e0, e1);
     ms /= reps;
     char b[128];
-    snprintf(b, sizeof b, "%s{\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d,\"ms\":%.5f}", first ? "" : ",",
-             c.pf, c.nw, c.wg_per_cu, ms);
+    snprintf(b, sizeof b, "%s{\"stage\":%d,\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d,\"ms\":%.5f}",
+             first ? "" : ",", c.stage, c.pf, c.nw, c.wg_per_cu, ms);
     rep += b;
     first = false;
     if (ms < best_ms) {
@@ -508,8 +548,9 @@ maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   char b[128];
-  snprintf(b, sizeof b, "],\"best\":{\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d,\"ms\":%.5f}}", best.pf,
-           best.nw, best.wg_per_cu, best_ms);
+  snprintf(b, sizeof b,
+           "],\"best\":{\"stage\":%d,\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d,\"ms\":%.5f}}",
+           best.stage, best.pf, best.nw, best.wg_per_cu, best_ms);
   rep += b;
   std::string all;
   {

@@ -91,7 +91,8 @@ __device__ __forceinline__ int sload_i32(const int32_t* p, int64_t i) {
   return ((const_i32_ptr)p)[i];
 }
 
-// 512 zero bytes (one chunk row of the widest element type): the target of the
-// fixed-count loads a wave issues when it has nothing left to load, so those
-// loads never depend on the caller's buffers being non-empty.
-static __device__ __attribute__((aligned(16))) char g_zero_row[512];
+// 1 KiB of zeros (one wave's worth of 16-byte lanes; at least one chunk row
+// of the widest element type): the target of the fixed-count loads a wave
+// issues when it has nothing left to load, so those loads never depend on the
+// caller's buffers being non-empty.
+static __device__ __attribute__((aligned(16))) char g_zero_row[1024];

@@ -118,13 +118,34 @@ __device__ int stage_query(const FusedParams& P, int64_t a, u32x4* q_lds, int nt
   return nq;
 }
 
-template <int DT, int NQB, int DCH, int PF, int NW, bool QREG>
+// LDS bytes of the per-wave staging ring of the STAGE variant.
+template <int DT, int DCH, int PF, int NW>
+constexpr size_t stage_ring_bytes() {
+  return (size_t)NW * PF * 16 * DCH * elem_size<DT>::value;
+}
+
+// s_waitcnt immediate for "at most n vector memory operations outstanding"
+// (vmcnt in bits 3:0 and 15:14; expcnt and lgkmcnt left at their maxima).
+constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8); }
+
+template <int DT, int NQB, int DCH, int PF, int NW, bool QREG, bool STAGE>
 __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
   extern __shared__ u32x4 q_lds[];
   constexpr int ESZ = elem_size<DT>::value;
   constexpr int CB = DCH * ESZ;  // bytes of one row within one chunk
   constexpr int NL = CB / 64;    // 16-byte loads per lane per step
   static_assert(NL >= 1, "chunk too narrow");
+  // STAGE: each step's tile (16 rows x CB bytes) arrives in a per-wave LDS
+  // ring through global_load_lds_dwordx4 (non-temporal): every wave
+  // instruction moves 1 KiB of consecutive rows, the fastest way this device
+  // streams HBM. Chunk p of tile row rho lands in LDS slot rho*CPR +
+  // (p ^ swz(rho)), so the 16 rows an MFMA operand read touches fall in 16
+  // different bank groups.
+  constexpr int TILE = 16 * CB;
+  constexpr int CPR = CB / 16;                    // 16-byte chunks per tile row
+  constexpr int SW = CPR < 16 ? CPR : 16;         // XOR width
+  constexpr int SWD = 16 / SW;                    // rows sharing a bank-group offset
+  constexpr int LOADS_PER_FILL = NL + (DT == DT_FP8 ? 1 : 0);
 
   const int lane = lane_id();
   const int r = lane & 15, g = lane >> 4;
@@ -223,19 +244,22 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       }
     };
 
-    u32x4 buf[PF][NL];
+    u32x4 buf[STAGE ? 1 : PF][NL];
     int bsc[PF];
     int flags[PF];
     int64_t fp[PF];
+    char* ring = (char*)q_lds + (size_t)NQB * 16 * P.row_bytes + (size_t)wave * PF * TILE;
+    auto swz = [](int row) { return (row / SWD) & (SW - 1); };
 
     // Every fill issues exactly NL (+1 for FP8) loads, from a harmless address
     // when there is nothing left to load, so the compiler's vmcnt accounting
     // sees a fixed depth of PF steps in flight.
-    auto fill = [&](u32x4 (&bb)[NL], int& sc, int& fl, int64_t& pp) {
+    auto fill = [&](const int s) {
       int f = 0;
       const char* base = g_zero_row;
       const float* sptr = (const float*)g_zero_row;
-      pp = cp;
+      const bool live = cp < hi && cnd != 0;
+      fp[s] = cp;
       if (cp < hi) {
         if (cnd == 0) {
           f = F_VALID | F_EMPTY;
@@ -252,14 +276,36 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
           }
         }
       }
+      if constexpr (STAGE) {
+        // uniform tile base + per-lane 32-bit offset; an idle fill reads row
+        // 0 of the zero block (offsets stay below CB <= 1 KiB)
+        const char* tb = g_zero_row;
+        int lim = 0;
+        if (live) {
+          tb = P.d_tok + (ct0 + ctile * 16) * P.row_bytes + cchunk * CB;
+          lim = cnd - 1 - ctile * 16;
+        }
+        char* slot = ring + s * TILE;
 #pragma unroll
-      for (int c = 0; c < NL; ++c) bb[c] = *(const u32x4*)(base + c * 64);
-      if constexpr (DT == DT_FP8) {
-        sc = e8m0_of(*sptr);
+        for (int w = 0; w < NL; ++w) {
+          const int ch = 64 * w + lane;  // LDS slot of this lane's 16 bytes
+          const int rho = ch / CPR, p = ch % CPR;
+          const unsigned off =
+              (unsigned)((rho < lim ? rho : lim) * P.row_bytes + (p ^ swz(rho)) * 16);
+          __builtin_amdgcn_global_load_lds((const void*)(tb + off),
+                                           (__attribute__((address_space(3))) void*)(slot + w * 1024),
+                                           16, 0, 2 /* non-temporal */);
+        }
       } else {
-        sc = 127;
+#pragma unroll
+        for (int c = 0; c < NL; ++c) buf[s][c] = *(const u32x4*)(base + c * 64);
       }
-      fl = f;
+      if constexpr (DT == DT_FP8) {
+        bsc[s] = e8m0_of(*sptr);
+      } else {
+        bsc[s] = 127;
+      }
+      flags[s] = f;
       if (cp < hi) {
         if (cnd == 0) {
           next_pair();
@@ -295,11 +341,25 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       if (lane == 0) P.scores[pp] = tot;
     };
 
-    auto consume = [&](const u32x4 (&bb)[NL], int sc, int fl, int64_t pp) {
+    auto consume = [&](const int s) {
+      const int fl = flags[s], sc = bsc[s];
+      const int64_t pp = fp[s];
       if (!(fl & F_VALID)) return;
       if (fl & F_EMPTY) {
         if (lane == 0) P.scores[pp] = nq == 0 ? 0.f : -__builtin_inff();
         return;
+      }
+      u32x4 bb[NL];
+      if constexpr (STAGE) {
+        // every later fill issued LOADS_PER_FILL vector memory operations
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm((PF - 1) * LOADS_PER_FILL));
+        const char* slot = ring + s * TILE;
+#pragma unroll
+        for (int c = 0; c < NL; ++c)
+          bb[c] = *(const u32x4*)(slot + (r * CPR + ((c * 4 + g) ^ swz(r))) * 16);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NL; ++c) bb[c] = buf[s][c];
       }
       if constexpr (QREG) {
         // one chunk per tile: every step starts and ends a tile
@@ -331,14 +391,14 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     };
 
 #pragma unroll
-    for (int s = 0; s < PF; ++s) fill(buf[s], bsc[s], flags[s], fp[s]);
+    for (int s = 0; s < PF; ++s) fill(s);
 
     if (flags[0] & F_VALID) {
       while (true) {
 #pragma unroll
         for (int s = 0; s < PF; ++s) {
-          consume(buf[s], bsc[s], flags[s], fp[s]);
-          fill(buf[s], bsc[s], flags[s], fp[s]);
+          consume(s);
+          fill(s);
         }
         // slots are filled in order: an invalid refill of slot 0 means the
         // cursor was exhausted before this round's refills, and every valid
@@ -346,6 +406,9 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
         if (!(flags[0] & F_VALID)) break;
       }
     }
+    // the idle refills still target this wave's ring: let them land before
+    // the next segment's fills reuse the slots
+    if constexpr (STAGE) __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
     pb = se;
   }
 }

@@ -11,9 +11,9 @@ namespace {
 
 constexpr int DT = FUSED_DT;
 
-template <int NQB, int DCH, int PF, int NW, bool QREG>
+template <int NQB, int DCH, int PF, int NW, bool QREG, bool STAGE>
 hipError_t launch_fused_t(const FusedParams& P, int grid, size_t lds, hipStream_t s) {
-  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QREG>;
+  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QREG, STAGE>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
@@ -23,9 +23,9 @@ hipError_t launch_fused_t(const FusedParams& P, int grid, size_t lds, hipStream_
   return hipGetLastError();
 }
 
-template <int NQB, int DCH, int PF, int NW, bool QREG>
+template <int NQB, int DCH, int PF, int NW, bool QREG, bool STAGE>
 int occupancy_fused_t(size_t lds) {
-  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QREG>;
+  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QREG, STAGE>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
           hipSuccess)
@@ -35,27 +35,36 @@ int occupancy_fused_t(size_t lds) {
   return nb;
 }
 
-template <int NQB, int DCH, int PF, int NW>
+template <int NQB, int DCH, int PF, int NW, bool STAGE>
 FusedFns pick_q(bool qreg) {
-  if (qreg) return {launch_fused_t<NQB, DCH, PF, NW, true>, occupancy_fused_t<NQB, DCH, PF, NW, true>};
-  return {launch_fused_t<NQB, DCH, PF, NW, false>, occupancy_fused_t<NQB, DCH, PF, NW, false>};
+  if (qreg)
+    return {launch_fused_t<NQB, DCH, PF, NW, true, STAGE>,
+            occupancy_fused_t<NQB, DCH, PF, NW, true, STAGE>, STAGE};
+  return {launch_fused_t<NQB, DCH, PF, NW, false, STAGE>,
+          occupancy_fused_t<NQB, DCH, PF, NW, false, STAGE>, STAGE};
 }
 
-template <int NQB, int DCH, int PF>
+template <int NQB, int DCH, int PF, bool STAGE>
 FusedFns pick_nw(int nw, bool qreg) {
-  return nw == 8 ? pick_q<NQB, DCH, PF, 8>(qreg) : pick_q<NQB, DCH, PF, 4>(qreg);
+  return nw == 8 ? pick_q<NQB, DCH, PF, 8, STAGE>(qreg) : pick_q<NQB, DCH, PF, 4, STAGE>(qreg);
+}
+
+template <int NQB, int DCH, bool STAGE>
+FusedFns pick_pf(int pf, int nw, bool qreg) {
+  if (pf == 2) return pick_nw<NQB, DCH, 2, STAGE>(nw, qreg);
+  if (pf == 3) return pick_nw<NQB, DCH, 3, STAGE>(nw, qreg);
+  return pick_nw<NQB, DCH, 4, STAGE>(nw, qreg);
 }
 
 template <int NQB, int DCH>
-FusedFns pick_pf(int pf, int nw, bool qreg) {
-  if (pf == 2) return pick_nw<NQB, DCH, 2>(nw, qreg);
-  if (pf == 3) return pick_nw<NQB, DCH, 3>(nw, qreg);
-  return pick_nw<NQB, DCH, 4>(nw, qreg);
+FusedFns pick_stage(int pf, int nw, bool qreg, bool stage) {
+  return stage ? pick_pf<NQB, DCH, true>(pf, nw, qreg) : pick_pf<NQB, DCH, false>(pf, nw, qreg);
 }
 
 template <int NQB>
-FusedFns pick_dch(int dch, int pf, int nw, bool qreg) {
-  return dch == 64 ? pick_pf<NQB, 64>(pf, nw, qreg) : pick_pf<NQB, 128>(pf, nw, qreg);
+FusedFns pick_dch(int dch, int pf, int nw, bool qreg, bool stage) {
+  return dch == 64 ? pick_stage<NQB, 64>(pf, nw, qreg, stage)
+                   : pick_stage<NQB, 128>(pf, nw, qreg, stage);
 }
 
 template <int NQB, int DCH>
@@ -90,10 +99,11 @@ hipError_t unfused_dch(const FusedParams& P, float* S, int grid, size_t lds, int
 #define CAT2(a, b) a##b
 #define CAT(a, b) CAT2(a, b)
 
-FusedFns CAT(fused_kernel_fns_, FUSED_DT)(int nqb, int dch, int pf, int nw, bool qreg) {
-  if (nqb == 1) return pick_dch<1>(dch, pf, nw, qreg);
-  if (nqb == 2) return pick_dch<2>(dch, pf, nw, qreg);
-  return pick_dch<4>(dch, pf, nw, qreg);
+FusedFns CAT(fused_kernel_fns_, FUSED_DT)(int nqb, int dch, int pf, int nw, bool qreg,
+                                           bool stage) {
+  if (nqb == 1) return pick_dch<1>(dch, pf, nw, qreg, stage);
+  if (nqb == 2) return pick_dch<2>(dch, pf, nw, qreg, stage);
+  return pick_dch<4>(dch, pf, nw, qreg, stage);
 }
 
 hipError_t CAT(launch_unfused_, FUSED_DT)(int nqb, int dch, const FusedParams& P, float* S,

@@ -32,11 +32,14 @@ typedef int (*fused_occ_fn)(size_t lds);
 struct FusedFns {
   fused_launch_fn launch;
   fused_occ_fn occupancy;
+  bool stage;
 };
 
 // dt: maxsim_dtype; nqb: query blocks of 16 (1, 2, 4); dch: 64 or 128;
-// pf: prefetch depth (2, 3, 4); nw: waves per workgroup (4, 8); qreg: Q in VGPRs.
-FusedFns fused_kernel_fns(int dt, int nqb, int dch, int pf, int nw, bool qreg);
+// pf: prefetch depth (2, 3, 4); nw: waves per workgroup (4, 8); qreg: Q in VGPRs;
+// stage: document tiles arrive through a per-wave LDS ring (pf slots of
+// 16 rows x dch elements per wave, after the query block) instead of VGPRs.
+FusedFns fused_kernel_fns(int dt, int nqb, int dch, int pf, int nw, bool qreg, bool stage);
 
 hipError_t launch_unfused(int dt, int nqb, int dch, const FusedParams& P, float* S, int grid,
                           size_t lds, hipStream_t s);
@@ -75,6 +78,10 @@ size_t topk_ws_bytes(int64_t n_seg, int k);
 // ---- input conversion ----
 hipError_t launch_quantize(const float* src, int64_t n_tokens, int dim, int dt, void* dst,
                            float* scales, hipStream_t s);
+
+// ---- measured read ceiling ----
+hipError_t launch_stream_probe(const void* buf, size_t bytes, int variant, uint32_t* sink,
+                               int grid, hipStream_t s);
 
 // ---- device properties ----
 int device_cu_count();

@@ -1,0 +1,127 @@
+// probe.hip -- measured HBM read ceiling: the fastest plain stream read this
+// device sustains, so the fused kernels can be reported against it as well
+// as against the published peak.
+//
+// Each wave reads one contiguous share of the buffer with 16-byte loads,
+// UNROLL loads in flight per lane, and folds them into an XOR that is stored
+// once per wave (so the loads cannot be removed).
+//   variant 0: plain loads, lane-contiguous (each wave instruction = 1 KiB)
+//   variant 1: the same with the non-temporal hint
+//   variant 2: the fused scorer's pattern: 16 rows of 256 B per 4 KiB tile,
+//              lane (r, g) reads row r at byte g*16 + c*64 (c < 4)
+//   variant 3: variant 2 with the non-temporal hint
+//   variant 4: lane-contiguous non-temporal loads straight into LDS
+//              (global_load_lds_dwordx4), read back with ds_read_b128
+#include "device_common.h"
+#include "kernels.h"
+
+namespace {
+
+template <int VARIANT>
+__global__ __launch_bounds__(256) void stream_read_kernel(const u32x4* __restrict__ buf,
+                                                          int64_t n16, uint32_t* __restrict__ sink) {
+  constexpr int UNROLL = 16;
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  // this wave's [lo, hi) in 16-byte units, whole 4 KiB tiles
+  const int64_t tiles = n16 / 256;
+  const int64_t t_lo = tiles * w / nw, t_hi = tiles * (w + 1) / nw;
+  u32x4 acc = {0, 0, 0, 0};
+  for (int64_t t = t_lo; t < t_hi; t += UNROLL / 4) {
+    u32x4 v[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      int64_t tile = t + u / 4;
+      if (tile >= t_hi) tile = t_hi - 1;
+      int64_t idx;
+      if constexpr (VARIANT == 2 || VARIANT == 3) {
+        const int r = lane & 15, g = lane >> 4, c = u & 3;
+        idx = tile * 256 + r * 16 + c * 4 + g;
+      } else {
+        idx = tile * 256 + (u & 3) * 64 + lane;
+      }
+      if constexpr (VARIANT == 1 || VARIANT == 3)
+        v[u] = __builtin_nontemporal_load(buf + idx);
+      else
+        v[u] = buf[idx];
+    }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) acc ^= v[u];
+  }
+  uint32_t x = acc.x ^ acc.y ^ acc.z ^ acc.w;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x ^= __shfl_xor(x, m, 64);
+  if (lane == 0) sink[w] = x;
+}
+
+// Variant 4: each wave owns a ring of 4 tiles (4 KiB each) in LDS; tile t+3
+// is requested while tile t is read back.
+__global__ __launch_bounds__(256) void stream_read_lds_kernel(const u32x4* __restrict__ buf,
+                                                              int64_t n16,
+                                                              uint32_t* __restrict__ sink) {
+  __shared__ u32x4 ring[4][4][256];  // [wave][slot][16-byte chunk]
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  const int64_t w = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t tiles = n16 / 256;
+  const int64_t t_lo = tiles * w / nw, t_hi = tiles * (w + 1) / nw;
+  u32x4 acc = {0, 0, 0, 0};
+  auto issue = [&](int64_t t, int slot) {
+    if (t >= t_hi) t = t_hi - 1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      __builtin_amdgcn_global_load_lds((const void*)(buf + t * 256 + c * 64 + lane),
+                                       (__attribute__((address_space(3))) void*)&ring[wv][slot][c * 64],
+                                       16, 0, 2 /* nt */);
+  };
+  if (t_lo < t_hi) {
+    issue(t_lo + 0, 0);
+    issue(t_lo + 1, 1);
+    issue(t_lo + 2, 2);
+    for (int64_t t = t_lo; t < t_hi; t += 4) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        issue(t + s + 3, (s + 3) & 3);
+        __builtin_amdgcn_s_waitcnt(0x0F7C);  // vmcnt(12): the oldest tile has landed
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc ^= ring[wv][s][c * 64 + lane];
+      }
+    }
+  }
+  uint32_t x = acc.x ^ acc.y ^ acc.z ^ acc.w;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x ^= __shfl_xor(x, m, 64);
+  if (lane == 0) sink[w] = x;
+}
+
+}  // namespace
+
+hipError_t launch_stream_probe(const void* buf, size_t bytes, int variant, uint32_t* sink,
+                               int grid, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  switch (variant) {
+    case 1:
+      hipLaunchKernelGGL(stream_read_kernel<1>, dim3(grid), dim3(256), 0, s, (const u32x4*)buf,
+                         n16, sink);
+      break;
+    case 2:
+      hipLaunchKernelGGL(stream_read_kernel<2>, dim3(grid), dim3(256), 0, s, (const u32x4*)buf,
+                         n16, sink);
+      break;
+    case 3:
+      hipLaunchKernelGGL(stream_read_kernel<3>, dim3(grid), dim3(256), 0, s, (const u32x4*)buf,
+                         n16, sink);
+      break;
+    case 4:
+      hipLaunchKernelGGL(stream_read_lds_kernel, dim3(grid), dim3(256), 0, s, (const u32x4*)buf,
+                         n16, sink);
+      break;
+    default:
+      hipLaunchKernelGGL(stream_read_kernel<0>, dim3(grid), dim3(256), 0, s, (const u32x4*)buf,
+                         n16, sink);
+      break;
+  }
+  return hipGetLastError();
+}

@@ -3,33 +3,45 @@
 // Every entry maps to a 64-bit key that orders exactly like the required
 // ranking: the high 32 bits are the score's bits made order-preserving as an
 // unsigned integer (NaN -> 0, below -inf), the low 32 bits are ~id so smaller
-// ids rank higher. The k-th largest key is found by an 8-pass radix select
-// (8 bits per pass, 256-bin histograms built in LDS, then merged with global
-// atomics); every pass's kernel first re-derives the running prefix from the
-// previous pass's histogram, so there is no separate scan launch. A gather
-// kernel then copies the (at most k) keys >= the threshold and one workgroup
-// per segment sorts them with a bitonic network in LDS. Integer keys only:
-// the result is exact and independent of launch shape.
+// ids rank higher. Five launches:
+//   init     zero the per-segment histograms and counters;
+//   hist0    4096-bin histogram of the top 12 key bits (LDS, then global);
+//   hist1    each block re-derives the bin b0 holding the k-th largest entry
+//            from hist0, then histograms the next 12 bits of the entries in
+//            b0; this fixes a 24-bit prefix P;
+//   compact  entries whose top 24 bits exceed P are certainly selected
+//            (fewer than k of them); entries equal to P form the boundary
+//            set, copied to a buffer of BOUND_CAP keys;
+//   sort     one workgroup per segment sorts the selected and boundary keys
+//            with a bitonic network in LDS and writes the first k. If the
+//            boundary set overflowed its buffer (massive exact ties), the
+//            workgroup instead finishes the selection with 8-bit radix passes
+//            over the segment, which is slower but exact.
+// Integer keys only: the result is exact and independent of launch shape.
 #include "device_common.h"
 #include "kernels.h"
 
 namespace {
 
 constexpr int TK_THREADS = 256;
+constexpr int TK_SORT_THREADS = 1024;
 constexpr int TK_MAXK = 1024;
+constexpr int BOUND_CAP = 4096;
+constexpr int SORT_CAP = 8192;  // >= TK_MAXK + BOUND_CAP, power of two
 
 struct SegWs {
-  uint32_t hist[8][256];
-  uint64_t prefix[9];
-  uint32_t remain[9];
-  uint32_t n_gt;
-  uint32_t n_eq;
-  uint32_t pad[5];
-  // followed by k uint64 candidate keys
+  uint32_t hist0[4096];
+  uint32_t hist1[4096];
+  uint32_t n_above;  // entries with a 24-bit prefix above P
+  uint32_t n_bound;  // entries with prefix P (may exceed BOUND_CAP)
+  uint32_t prefix;   // P
+  uint32_t rem;      // how many boundary entries belong to the top k
+  uint32_t pad[4];
+  // followed by uint64 above[TK_MAXK] and uint64 bound[BOUND_CAP]
 };
 
-__host__ __device__ inline size_t seg_ws_bytes(int k) {
-  size_t b = sizeof(SegWs) + (size_t)k * 8;
+__host__ __device__ inline size_t seg_ws_bytes() {
+  size_t b = sizeof(SegWs) + (size_t)(TK_MAXK + BOUND_CAP) * 8;
   return (b + 255) & ~(size_t)255;
 }
 
@@ -43,135 +55,149 @@ __device__ __forceinline__ float key_score(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
 }
 
-__device__ __forceinline__ uint64_t full_key(const float* scores, const int32_t* ids, int64_t i,
+__device__ __forceinline__ uint64_t full_key(uint32_t sk, const int32_t* ids, int64_t i,
                                              int64_t start) {
   uint32_t id = ids ? (uint32_t)ids[i] : (uint32_t)(i - start);
-  return ((uint64_t)score_key(scores[i]) << 32) | (uint64_t)(0xFFFFFFFFu - id);
+  return ((uint64_t)sk << 32) | (uint64_t)(0xFFFFFFFFu - id);
 }
 
-__device__ __forceinline__ SegWs* seg_ws(void* ws, int64_t s, int k) {
-  return (SegWs*)((char*)ws + (size_t)s * seg_ws_bytes(k));
+__device__ __forceinline__ SegWs* seg_ws(void* ws, int64_t s) {
+  return (SegWs*)((char*)ws + (size_t)s * seg_ws_bytes());
 }
 
-__global__ __launch_bounds__(TK_THREADS) void topk_init_kernel(void* ws, int k) {
-  SegWs* w = seg_ws(ws, blockIdx.x, k);
-  for (int i = threadIdx.x; i < 8 * 256; i += TK_THREADS) (&w->hist[0][0])[i] = 0u;
+// Block-wide: the bin holding the rem-th largest entry of a 4096-bin
+// histogram, and how many entries lie in higher bins. Every thread returns
+// the same values.
+__device__ void select_bin(const uint32_t* __restrict__ hist, uint32_t rem, uint32_t* sh,
+                           uint32_t& bin, uint32_t& above) {
+  // sh: 4096 + 2 words of shared scratch. Suffix sums over bins, high to low.
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int per = 4096 / nt;  // bins per thread (nt divides 4096)
+  // bins of thread t: [4096 - (t+1)*per, 4096 - t*per), visited high to low
+  uint32_t local = 0;
+  const int hi = 4096 - t * per;
+  for (int b = hi - 1; b >= hi - per; --b) local += hist[b];
+  sh[t] = local;
+  __syncthreads();
+  if (t == 0) {  // exclusive prefix over threads (small: nt entries)
+    uint32_t run = 0;
+    for (int i = 0; i < nt; ++i) {
+      uint32_t v = sh[i];
+      sh[i] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  uint32_t run = sh[t];
+  if (run < rem && run + local >= rem) {
+    for (int b = hi - 1; b >= hi - per; --b) {
+      uint32_t h = hist[b];
+      if (run + h >= rem) {
+        sh[4096] = (uint32_t)b;
+        sh[4097] = run;
+        break;
+      }
+      run += h;
+    }
+  }
+  __syncthreads();
+  bin = sh[4096];
+  above = sh[4097];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(TK_THREADS) void topk_init_kernel(void* ws) {
+  SegWs* w = seg_ws(ws, blockIdx.x);
+  for (int i = threadIdx.x; i < 8192; i += TK_THREADS) (&w->hist0[0])[i] = 0u;
   if (threadIdx.x == 0) {
-    w->prefix[0] = 0;
-    w->remain[0] = (uint32_t)k;
-    w->n_gt = 0;
-    w->n_eq = 0;
+    w->n_above = 0;
+    w->n_bound = 0;
+    w->prefix = 0;
+    w->rem = 0;
   }
 }
 
-// Given the histogram of pass p (digit bits 56-8p .. 63-8p) and the state
-// before it, the state after it: the digit holding the remain-th largest
-// element among those that match the prefix.
-__device__ void derive_state(const SegWs* w, int p, uint64_t& prefix, uint32_t& remain) {
-  uint64_t pre = w->prefix[p];
-  uint32_t rem = w->remain[p];
-  uint32_t cum = 0;
-  int d = 255;
-  for (; d > 0; --d) {
-    uint32_t h = w->hist[p][d];
-    if (cum + h >= rem) break;
-    cum += h;
-  }
-  prefix = pre | ((uint64_t)d << (56 - 8 * p));
-  remain = rem - cum;
-}
-
-__global__ __launch_bounds__(TK_THREADS) void topk_hist_kernel(const float* __restrict__ scores,
-                                                               const int64_t* __restrict__ seg_off,
-                                                               const int32_t* __restrict__ ids,
-                                                               void* ws, int k, int pass) {
-  __shared__ uint32_t h[256];
-  __shared__ uint64_t s_prefix;
+__global__ __launch_bounds__(TK_THREADS) void topk_hist0_kernel(const float* __restrict__ scores,
+                                                                const int64_t* __restrict__ seg_off,
+                                                                void* ws, int k) {
+  __shared__ uint32_t h[4096];
   const int64_t s = blockIdx.y;
   const int64_t start = seg_off[s], end = seg_off[s + 1];
   if (end - start <= k) return;  // everything is selected
-  SegWs* w = seg_ws(ws, s, k);
-  h[threadIdx.x] = 0u;
-  if (threadIdx.x == 0) {
-    uint64_t pre = 0;
-    uint32_t rem = (uint32_t)k;
-    if (pass > 0) derive_state(w, pass - 1, pre, rem);
-    s_prefix = pre;
-    if (blockIdx.x == 0 && pass > 0) {
-      w->prefix[pass] = pre;
-      w->remain[pass] = rem;
-    }
-  }
+  for (int i = threadIdx.x; i < 4096; i += TK_THREADS) h[i] = 0u;
   __syncthreads();
-  const uint64_t pre = s_prefix;
-  const int shift = 56 - 8 * pass;
-  const uint64_t hi_mask = pass == 0 ? 0ull : (~0ull << (64 - 8 * pass));
   for (int64_t i = start + (int64_t)blockIdx.x * TK_THREADS + threadIdx.x; i < end;
-       i += (int64_t)gridDim.x * TK_THREADS) {
-    uint64_t key = full_key(scores, ids, i, start);
-    if ((key & hi_mask) == pre) atomicAdd(&h[(key >> shift) & 255], 1u);
-  }
+       i += (int64_t)gridDim.x * TK_THREADS)
+    atomicAdd(&h[score_key(scores[i]) >> 20], 1u);
   __syncthreads();
-  uint32_t c = h[threadIdx.x];
-  if (c) atomicAdd(&w->hist[pass][threadIdx.x], c);
+  SegWs* w = seg_ws(ws, s);
+  for (int i = threadIdx.x; i < 4096; i += TK_THREADS)
+    if (h[i]) atomicAdd(&w->hist0[i], h[i]);
 }
 
-__global__ __launch_bounds__(TK_THREADS) void topk_gather_kernel(const float* __restrict__ scores,
-                                                                 const int64_t* __restrict__ seg_off,
-                                                                 const int32_t* __restrict__ ids,
-                                                                 void* ws, int k) {
-  __shared__ uint64_t s_thr;
-  __shared__ uint32_t s_rem;
+__global__ __launch_bounds__(TK_THREADS) void topk_hist1_kernel(const float* __restrict__ scores,
+                                                                const int64_t* __restrict__ seg_off,
+                                                                void* ws, int k) {
+  __shared__ uint32_t h[4096 + 2];
   const int64_t s = blockIdx.y;
   const int64_t start = seg_off[s], end = seg_off[s + 1];
-  SegWs* w = seg_ws(ws, s, k);
-  uint64_t* cand = (uint64_t*)(w + 1);
+  if (end - start <= k) return;
+  SegWs* w = seg_ws(ws, s);
+  uint32_t b0, above0;
+  select_bin(w->hist0, (uint32_t)k, h, b0, above0);
+  for (int i = threadIdx.x; i < 4096; i += TK_THREADS) h[i] = 0u;
+  __syncthreads();
+  for (int64_t i = start + (int64_t)blockIdx.x * TK_THREADS + threadIdx.x; i < end;
+       i += (int64_t)gridDim.x * TK_THREADS) {
+    uint32_t key = score_key(scores[i]);
+    if ((key >> 20) == b0) atomicAdd(&h[(key >> 8) & 0xFFF], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 4096; i += TK_THREADS)
+    if (h[i]) atomicAdd(&w->hist1[i], h[i]);
+}
+
+__global__ __launch_bounds__(TK_THREADS) void topk_compact_kernel(
+    const float* __restrict__ scores, const int64_t* __restrict__ seg_off,
+    const int32_t* __restrict__ ids, void* ws, int k) {
+  __shared__ uint32_t h[4096 + 2];
+  const int64_t s = blockIdx.y;
+  const int64_t start = seg_off[s], end = seg_off[s + 1];
+  SegWs* w = seg_ws(ws, s);
+  uint64_t* above = (uint64_t*)(w + 1);
+  uint64_t* bound = above + TK_MAXK;
   if (end - start <= k) {
     for (int64_t i = start + (int64_t)blockIdx.x * TK_THREADS + threadIdx.x; i < end;
          i += (int64_t)gridDim.x * TK_THREADS)
-      cand[i - start] = full_key(scores, ids, i, start);
+      above[i - start] = full_key(score_key(scores[i]), ids, i, start);
     return;
   }
-  if (threadIdx.x == 0) {
-    uint64_t thr;
-    uint32_t rem;
-    derive_state(w, 7, thr, rem);
-    s_thr = thr;
-    s_rem = rem;
+  uint32_t b0, above0, b1, above1;
+  select_bin(w->hist0, (uint32_t)k, h, b0, above0);
+  select_bin(w->hist1, (uint32_t)k - above0, h, b1, above1);
+  const uint32_t prefix = (b0 << 12) | b1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    w->prefix = prefix;
+    w->rem = (uint32_t)k - above0 - above1;
   }
-  __syncthreads();
-  const uint64_t thr = s_thr;
-  const uint32_t rem = s_rem;
-  const uint32_t n_above = (uint32_t)k - rem;
   for (int64_t i = start + (int64_t)blockIdx.x * TK_THREADS + threadIdx.x; i < end;
        i += (int64_t)gridDim.x * TK_THREADS) {
-    uint64_t key = full_key(scores, ids, i, start);
-    if (key > thr) {
-      uint32_t slot = atomicAdd(&w->n_gt, 1u);
-      if (slot < n_above) cand[slot] = key;
-    } else if (key == thr) {
-      uint32_t e = atomicAdd(&w->n_eq, 1u);
-      if (e < rem) cand[n_above + e] = key;
+    uint32_t key = score_key(scores[i]);
+    uint32_t hi = key >> 8;
+    if (hi > prefix) {
+      uint32_t slot = atomicAdd(&w->n_above, 1u);
+      if (slot < TK_MAXK) above[slot] = full_key(key, ids, i, start);
+    } else if (hi == prefix) {
+      uint32_t slot = atomicAdd(&w->n_bound, 1u);
+      if (slot < BOUND_CAP) bound[slot] = full_key(key, ids, i, start);
     }
   }
 }
 
-__global__ __launch_bounds__(TK_MAXK) void topk_sort_kernel(const int64_t* __restrict__ seg_off,
-                                                            void* ws, int k, int kpow2,
-                                                            float* __restrict__ out_scores,
-                                                            int32_t* __restrict__ out_ids) {
-  __shared__ uint64_t keys[TK_MAXK];
-  const int64_t s = blockIdx.x;
-  const int64_t n = seg_off[s + 1] - seg_off[s];
-  const int count = n < k ? (int)n : k;
-  SegWs* w = seg_ws(ws, s, k);
-  const uint64_t* cand = (const uint64_t*)(w + 1);
-  for (int i = threadIdx.x; i < kpow2; i += blockDim.x) keys[i] = i < count ? cand[i] : 0ull;
-  __syncthreads();
-  // bitonic sort, descending
-  for (int size = 2; size <= kpow2; size <<= 1) {
+__device__ void bitonic_desc(uint64_t* keys, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < kpow2; i += blockDim.x) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
         int j = i ^ stride;
         if (j > i) {
           bool desc = (i & size) == 0;
@@ -184,6 +210,89 @@ __global__ __launch_bounds__(TK_MAXK) void topk_sort_kernel(const int64_t* __res
       }
       __syncthreads();
     }
+  }
+}
+
+__global__ __launch_bounds__(TK_SORT_THREADS) void topk_sort_kernel(
+    const float* __restrict__ scores, const int64_t* __restrict__ seg_off,
+    const int32_t* __restrict__ ids, void* ws, int k, float* __restrict__ out_scores,
+    int32_t* __restrict__ out_ids) {
+  __shared__ uint64_t keys[SORT_CAP];
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t s_pre;
+  __shared__ uint32_t s_cnt[2];
+  const int64_t s = blockIdx.x;
+  const int64_t start = seg_off[s], end = seg_off[s + 1];
+  const int64_t n = end - start;
+  SegWs* w = seg_ws(ws, s);
+  const uint64_t* above = (const uint64_t*)(w + 1);
+  const uint64_t* bound = above + TK_MAXK;
+  int count;  // keys placed at the front of `keys`, already the top `count`
+  if (n <= k) {
+    count = (int)n;
+    int p2 = 1;
+    while (p2 < count) p2 <<= 1;
+    for (int i = threadIdx.x; i < p2; i += blockDim.x) keys[i] = i < count ? above[i] : 0ull;
+    __syncthreads();
+    bitonic_desc(keys, p2);
+  } else if (w->n_bound <= BOUND_CAP) {
+    const int na = (int)w->n_above, nb = (int)w->n_bound;
+    const int tot = na + nb;
+    int p2 = 1;
+    while (p2 < tot) p2 <<= 1;
+    for (int i = threadIdx.x; i < p2; i += blockDim.x)
+      keys[i] = i < na ? above[i] : (i < tot ? bound[i - na] : 0ull);
+    __syncthreads();
+    bitonic_desc(keys, p2);
+    count = k;
+  } else {
+    // Boundary overflow: the top-k all have key >= (P << 40); finish the
+    // radix select on the low 40 bits with 8-bit digits over the segment.
+    uint64_t pre = (uint64_t)w->prefix << 40;
+    uint32_t rem = w->rem;
+    for (int shift = 32; shift >= 0; shift -= 8) {
+      for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0u;
+      __syncthreads();
+      const uint64_t hmask = ~0ull << (shift + 8);
+      for (int64_t i = start + threadIdx.x; i < end; i += blockDim.x) {
+        uint64_t key = full_key(score_key(scores[i]), ids, i, start);
+        if ((key & hmask) == pre) atomicAdd(&hist[(key >> shift) & 255], 1u);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t cum = 0;
+        int d = 255;
+        for (; d > 0; --d) {
+          if (cum + hist[d] >= rem) break;
+          cum += hist[d];
+        }
+        s_pre = pre | ((uint64_t)d << shift);
+        s_cnt[0] = rem - cum;
+      }
+      __syncthreads();
+      pre = s_pre;
+      rem = s_cnt[0];
+      __syncthreads();
+    }
+    // pre is now the exact k-th key; collect every key >= pre (k of them,
+    // more only if an (id, score) pair repeats inside the segment)
+    if (threadIdx.x == 0) s_cnt[1] = 0;
+    __syncthreads();
+    for (int64_t i = start + threadIdx.x; i < end; i += blockDim.x) {
+      uint64_t key = full_key(score_key(scores[i]), ids, i, start);
+      if (key >= pre) {
+        uint32_t slot = atomicAdd(&s_cnt[1], 1u);
+        if (slot < (uint32_t)SORT_CAP) keys[slot] = key;
+      }
+    }
+    __syncthreads();
+    const int got = s_cnt[1] < (uint32_t)SORT_CAP ? (int)s_cnt[1] : SORT_CAP;
+    int p2 = 1;
+    while (p2 < got || p2 < k) p2 <<= 1;
+    for (int i = got + threadIdx.x; i < p2; i += blockDim.x) keys[i] = 0ull;
+    __syncthreads();
+    bitonic_desc(keys, p2);
+    count = k;
   }
   for (int i = threadIdx.x; i < k; i += blockDim.x) {
     float sc = -__builtin_inff();
@@ -200,7 +309,10 @@ __global__ __launch_bounds__(TK_MAXK) void topk_sort_kernel(const int64_t* __res
 
 }  // namespace
 
-size_t topk_ws_bytes(int64_t n_seg, int k) { return (size_t)n_seg * seg_ws_bytes(k); }
+size_t topk_ws_bytes(int64_t n_seg, int k) {
+  (void)k;
+  return (size_t)n_seg * seg_ws_bytes();
+}
 
 hipError_t launch_topk(const float* scores, const int64_t* seg_off, int64_t n_seg, int64_t n_total,
                        const int32_t* ids, int k, float* out_scores, int32_t* out_ids, void* ws,
@@ -210,16 +322,13 @@ hipError_t launch_topk(const float* scores, const int64_t* seg_off, int64_t n_se
   int64_t bps = avg / (TK_THREADS * 16);
   if (bps < 1) bps = 1;
   if (bps > 256) bps = 256;
-  hipLaunchKernelGGL(topk_init_kernel, dim3((unsigned)n_seg), dim3(TK_THREADS), 0, st, ws, k);
-  for (int p = 0; p < 8; ++p)
-    hipLaunchKernelGGL(topk_hist_kernel, dim3((unsigned)bps, (unsigned)n_seg), dim3(TK_THREADS),
-                       0, st, scores, seg_off, ids, ws, k, p);
-  hipLaunchKernelGGL(topk_gather_kernel, dim3((unsigned)bps, (unsigned)n_seg), dim3(TK_THREADS), 0,
-                     st, scores, seg_off, ids, ws, k);
-  int kpow2 = 1;
-  while (kpow2 < k) kpow2 <<= 1;
-  int threads = kpow2 < 64 ? 64 : kpow2;
-  hipLaunchKernelGGL(topk_sort_kernel, dim3((unsigned)n_seg), dim3(threads), 0, st, seg_off, ws, k,
-                     kpow2, out_scores, out_ids);
+  const dim3 grid((unsigned)bps, (unsigned)n_seg);
+  hipLaunchKernelGGL(topk_init_kernel, dim3((unsigned)n_seg), dim3(TK_THREADS), 0, st, ws);
+  hipLaunchKernelGGL(topk_hist0_kernel, grid, dim3(TK_THREADS), 0, st, scores, seg_off, ws, k);
+  hipLaunchKernelGGL(topk_hist1_kernel, grid, dim3(TK_THREADS), 0, st, scores, seg_off, ws, k);
+  hipLaunchKernelGGL(topk_compact_kernel, grid, dim3(TK_THREADS), 0, st, scores, seg_off, ids, ws,
+                     k);
+  hipLaunchKernelGGL(topk_sort_kernel, dim3((unsigned)n_seg), dim3(TK_SORT_THREADS), 0, st, scores,
+                     seg_off, ids, ws, k, out_scores, out_ids);
   return hipGetLastError();
 }

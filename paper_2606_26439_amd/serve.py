@@ -162,37 +162,73 @@ class Backend:
 
 class GpuBackend(Backend):
     """Launches a batch as one fused scoring call and one top-k call on a
-    stream of its own; completion is an event poll."""
+    stream of its own; completion is an event poll.
 
-    def __init__(self, pool_docs, pool_pq=None, k: int = 100, n_streams: int = 2,
+    Each in-flight slot owns a stream, a pinned host staging buffer and a
+    device input buffer (grown on demand, then reused), so a batch costs one
+    packed host-to-device copy, the conversion of its query tokens, the
+    scoring launch, the top-k launches and one device-to-host copy of the
+    top-k rows."""
+
+    def __init__(self, pool_docs, pool_pq=None, k: int = 100, n_slots: int = 3,
                  device: str = "cuda"):
         import torch
         from . import _binding as B
         self.torch, self.B = torch, B
         self.docs, self.pq, self.k, self.device = pool_docs, pool_pq, k, device
-        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
-        self._rr = 0
+        self.slots = [dict(stream=torch.cuda.Stream(device=device), busy=False, cap=0)
+                      for _ in range(n_slots)]
+
+    def _slot(self):
+        for sl in self.slots:
+            if not sl["busy"]:
+                return sl
+        raise RuntimeError("no free execution slot (scheduler admitted too many batches)")
+
+    def _ensure(self, sl, nbytes, n_req):
+        torch = self.torch
+        if sl["cap"] < nbytes:
+            cap = max(nbytes, 2 * sl["cap"], 1 << 20)
+            sl["host"] = torch.empty(cap, dtype=torch.uint8, pin_memory=True)
+            sl["dev"] = torch.empty(cap, dtype=torch.uint8, device=self.device)
+            sl["cap"] = cap
+        if sl.get("nreq", 0) < n_req:
+            n = max(n_req, 2 * sl.get("nreq", 0), 16)
+            sl["out_s"] = torch.empty((n, self.k), dtype=torch.float32, pin_memory=True)
+            sl["out_i"] = torch.empty((n, self.k), dtype=torch.int32, pin_memory=True)
+            sl["nreq"] = n
 
     def launch(self, batch: Batch):
         torch, B = self.torch, self.B
         reqs = batch.requests
-        s = self.streams[self._rr % len(self.streams)]
-        self._rr += 1
-        nq = np.array([len(r.query) for r in reqs], np.int64)
-        nc = np.array([len(r.cand_ids) for r in reqs], np.int64)
-        q_off = np.zeros(len(reqs) + 1, np.int64)
+        sl = self._slot()
+        s = sl["stream"]
+        nq = np.fromiter((len(r.query) for r in reqs), np.int64, len(reqs))
+        nc = np.fromiter((len(r.cand_ids) for r in reqs), np.int64, len(reqs))
+        dim = reqs[0].query.shape[1]
+        tq, tc, n = int(nq.sum()), int(nc.sum()), len(reqs)
+        # packed layout: q_off | c_off (int64) | query tokens (f32) | ids (i32)
+        o_q, o_c = 0, 8 * (n + 1)
+        o_tok = o_c + 8 * (n + 1)
+        o_ids = o_tok + 4 * tq * dim
+        nbytes = o_ids + 4 * tc
+        self._ensure(sl, nbytes, n)
+        h = sl["host"].numpy()
+        q_off = h[o_q:o_c].view(np.int64)
+        q_off[0] = 0
         np.cumsum(nq, out=q_off[1:])
-        c_off = np.zeros(len(reqs) + 1, np.int64)
+        c_off = h[o_c:o_tok].view(np.int64)
+        c_off[0] = 0
         np.cumsum(nc, out=c_off[1:])
-        q_host = torch.from_numpy(np.concatenate([r.query for r in reqs]).astype(np.float32)).pin_memory()
-        ids_host = torch.from_numpy(np.concatenate([r.cand_ids for r in reqs]).astype(np.int32)).pin_memory()
-        qoff_host = torch.from_numpy(q_off).pin_memory()
-        coff_host = torch.from_numpy(c_off).pin_memory()
+        np.concatenate([r.query for r in reqs], out=h[o_tok:o_ids].view(np.float32).reshape(tq, dim))
+        np.concatenate([r.cand_ids for r in reqs], out=h[o_ids:nbytes].view(np.int32))
+        d = sl["dev"]
         with torch.cuda.stream(s):
-            q32 = q_host.to(self.device, non_blocking=True)
-            ids = ids_host.to(self.device, non_blocking=True)
-            qoff = qoff_host.to(self.device, non_blocking=True)
-            coff = coff_host.to(self.device, non_blocking=True)
+            d[:nbytes].copy_(sl["host"][:nbytes], non_blocking=True)
+            qoff = d[o_q:o_c].view(torch.int64)
+            coff = d[o_c:o_tok].view(torch.int64)
+            q32 = d[o_tok:o_ids].view(torch.float32).view(tq, dim)
+            ids = d[o_ids:nbytes].view(torch.int32)
             cand = B.Candidates(coff, ids)
             if batch.mode == "pq":
                 qt, _ = B.quantize(q32, "f16", stream=s)
@@ -202,24 +238,25 @@ class GpuBackend(Backend):
                 qt, qs = B.quantize(q32, self.docs.dtype, stream=s)
                 Q = B.Tokens(qt, qoff, self.docs.dtype, qs, max_len=int(nq.max()))
                 scores = B.score(Q, self.docs, cand, stream=s)
-            ts, ti = B.topk(scores, coff, self.k, ids=ids, n_total=int(c_off[-1]), stream=s)
-            ts_h = torch.empty(ts.shape, dtype=ts.dtype, pin_memory=True)
-            ti_h = torch.empty(ti.shape, dtype=ti.dtype, pin_memory=True)
-            ts_h.copy_(ts, non_blocking=True)
-            ti_h.copy_(ti, non_blocking=True)
+            ts, ti = B.topk(scores, coff, self.k, ids=ids, n_total=tc, stream=s)
+            sl["out_s"][:n].copy_(ts, non_blocking=True)
+            sl["out_i"][:n].copy_(ti, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        # keep every device buffer alive until the event completes
-        return (ev, ts_h, ti_h, (q32, ids, qoff, coff, qt, scores, ts, ti))
+        sl["busy"] = True
+        # the device temporaries stay referenced until the event has completed
+        return (ev, sl, n, (qt, scores, ts, ti))
 
     def poll(self, handle) -> bool:
         return handle[0].query()
 
     def results(self, handle):
-        ev, ts_h, ti_h, _ = handle
+        ev, sl, n, _ = handle
         ev.synchronize()
-        return [(ti_h[i].numpy().astype(np.int64), ts_h[i].numpy().copy())
-                for i in range(ts_h.shape[0])]
+        out_s, out_i = sl["out_s"].numpy(), sl["out_i"].numpy()
+        res = [(out_i[i].astype(np.int64), out_s[i].copy()) for i in range(n)]
+        sl["busy"] = False
+        return res
 
 
 class Server:

@@ -3,6 +3,8 @@
 Sizes keep the oracle to seconds while spanning several 16-row tiles, ragged
 tails, empty documents, every query-token capacity and every d-chunk width.
 """
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -148,6 +150,49 @@ def test_scores_do_not_depend_on_launch_shape():
     assert np.array_equal(M.score(Q, D).cpu().numpy(), ref)
 
 
+_DT_CODE = {"f32": 0, "bf16": 1, "f16": 2, "fp8": 3}
+
+
+def _force_cfg(tmp_path, dtype, dim, stage, pf, nw, wg_per_cu=0):
+    entries = [{"dtype": _DT_CODE[dtype], "dim": dim, "nqb": nqb, "pf": pf, "nw": nw,
+                "wg_per_cu": wg_per_cu, "stage": stage} for nqb in (1, 2, 4)]
+    path = tmp_path / f"cfg_{dtype}_{dim}_{stage}_{pf}_{nw}.json"
+    path.write_text(json.dumps({"version": 1, "entries": entries}))
+    M.load_tune_cache(str(path))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("dim", [64, 128, 256])
+def test_every_launch_configuration_is_bit_identical(tmp_path, dtype, dim):
+    # Register-direct and LDS-staged tiles, every prefetch depth and
+    # workgroup size: the same wave-level arithmetic, so the same bits.
+    q, q_off, d, d_off = _ragged(90, dim, seed=dim + 61, nq_lens=[32, 7, 64, 16], empty_every=29)
+    Q = device_tokens(q, q_off, dtype)
+    D = device_tokens(d, d_off, dtype)
+    want = o1_scores(q, q_off, d, d_off, dtype)
+    esz = {"f32": 4, "bf16": 2, "f16": 2, "fp8": 1}[dtype]
+    dch = 128 if dim % 128 == 0 else 64
+    ref = None
+    try:
+        for stage in (0, 1):
+            for pf in (2, 3, 4):
+                for nw in (4, 8):
+                    _force_cfg(tmp_path, dtype, dim, stage, pf, nw)
+                    lds = 4 * 16 * dim * esz + stage * nw * pf * 16 * dch * esz
+                    if lds > 160 * 1024:
+                        with pytest.raises(M.MaxSimError):
+                            M.score(Q, D)
+                        continue
+                    got = M.score(Q, D).cpu().numpy()
+                    if ref is None:
+                        ref = got
+                        assert_close_o1(got, want, f"{dtype} d={dim}", dtype)
+                    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (stage, pf, nw)
+    finally:
+        _force_cfg(tmp_path, dtype, dim, 0, 2 if dtype == "f32" else 4, 4)
+        M.load_tune_cache(M.default_tune_cache())
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f16", "fp8"])
 def test_unfused_comparator(dtype):
     q, q_off, d, d_off = _ragged(500, 128, seed=41, nq_lens=[32, 12], empty_every=97)
@@ -177,10 +222,12 @@ def test_query_capacity_is_enforced():
 
 @pytest.mark.parametrize("k", [1, 7, 100])
 def test_topk_bit_exact(k):
-    sizes = [0, 5, 100, 1000, 3, 70000, 130]
+    # the last segment has only 3 distinct scores: its boundary set of equal
+    # scores overflows the compaction buffer and takes the exact radix path
+    sizes = [0, 5, 100, 1000, 3, 70000, 130, 20000]
+    distinct = [None, None, 40, None, None, None, 40, 3]
     off = W.offsets_from_lengths(sizes)
-    parts = [W.random_scores(s, seed=i, n_distinct=(None if i % 2 else 40))
-             for i, s in enumerate(sizes)]
+    parts = [W.random_scores(s, seed=i, n_distinct=distinct[i]) for i, s in enumerate(sizes)]
     s = np.concatenate(parts).astype(np.float32)
     s[off[1] + 1] = -np.inf
     s[off[1] + 3] = np.nan

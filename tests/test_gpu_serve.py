@@ -45,7 +45,7 @@ def _clone(r):
 
 def test_alone_equals_mixed(pool):
     reqs = _requests(60)
-    be = S.GpuBackend(pool["docs"], pool["pq"], k=100)
+    be = S.GpuBackend(pool["docs"], pool["pq"], k=100, n_slots=3)
     mixed = [_clone(r) for r in reqs]
     t0 = 0.0
     arr = W.poisson_arrivals(len(mixed), 20000.0, seed=9)
