@@ -45,6 +45,18 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def tuned_entry(path, dtype, dim, nqb):
+    """The tuned launch configuration the library loaded for a key (None:
+    the library's built-in default)."""
+    try:
+        for e in json.load(open(path))["entries"]:
+            if (e["dtype"], e["dim"], e["nqb"]) == (dtype, dim, nqb):
+                return e
+    except (OSError, ValueError, KeyError, TypeError):
+        pass
+    return None
+
+
 def measured_traffic(n_launch_bytes_alg):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
@@ -475,6 +487,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK,
                      "traffic": measured_traffic(alg),
                      "kernel": "fused_maxsim_kernel<f16, NQB=2, DCH=128>",
+                     "launch_config": tuned_entry(args.tune_cache, 2, wl.dim, 2),
                      "alg_bytes_per_launch": alg,
                      "launch_ms_mean": float(fused_ms.mean()),
                      "launch_ms_median": float(np.median(fused_ms))},
