@@ -287,6 +287,9 @@ def bench_pq(n_docs=2_000_000, n_queries=64, nq=32, M_=8, K=256, dsub=16):
     D = M.PQDocs(torch.from_numpy(cb_np).cuda(), codes, torch.from_numpy(d_off_np).cuda())
     n_pairs = n_queries * n_docs
     sc = torch.empty(n_pairs, dtype=torch.float32, device="cuda")
+    # both PQ scorers timed on this problem; the faster stays selected
+    tune = M.pq_autotune(Q, D, reps=2)
+    log(f"[bench] PQ scorers: {tune['trials']}")
     med, mean, std = time_fn(lambda: M.pq_score(Q, D, out=sc), 3, 1)
     # sampled check: 3 queries x 300 docs, decode-then-score in FP64
     g = np.random.default_rng(13)
@@ -313,7 +316,12 @@ def bench_pq(n_docs=2_000_000, n_queries=64, nq=32, M_=8, K=256, dsub=16):
            "lds_gathers_per_s": gathers / (med * 1e-3),
            "lds_gather_frac": gathers / (med * 1e-3) / lds_peak_gathers,
            "hbm_frac_of_codes_once": hb / (med * 1e-3) / HBM_PEAK,
-           "sampled_max_rel_err_vs_decode_then_score": worst}
+           "sampled_max_rel_err_vs_decode_then_score": worst,
+           "scorer": "decode-into-MFMA" if tune["best"]["variant"] == 1 else "table in LDS",
+           "scorer_trials_ms": tune["trials"]}
+    if tune["best"]["variant"] == 1:
+        fl = 2.0 * n_queries * nq * M_ * dsub * T
+        rec["mfma_f16_frac_unpadded"] = fl / (med * 1e-3) / R.PEAK_FLOPS["f16"]
     log(f"[bench] PQ: {med:.2f} ms, {rec['pairs_per_s'] / 1e9:.2f} G pairs/s, "
         f"LDS gather frac {rec['lds_gather_frac'] * 100:.1f}%, err {worst:.1e}")
     del codes, sc

@@ -208,8 +208,28 @@ maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
                               const maxsim_candidates* cand, float* scores, void* workspace,
                               size_t ws_bytes, maxsim_stream_t stream, int32_t reps,
                               const char* cache_path, char* report, size_t report_len);
-/* Loads tuned configurations written by maxsim_autotune (missing file: OK, no-op). */
+/* Loads tuned configurations written by maxsim_autotune or
+ * maxsim_pq_autotune (missing file: OK, no-op). */
 maxsim_status maxsim_load_tune_cache(const char* cache_path);
+
+/*
+ * PQ scorer choice (Sec. 4.3 Phase 2, and the same scores through the ADC
+ * identity of Sec. 4.2): maxsim_pq_score runs either the per-query table
+ * kernel (variant 0) or a decode-into-MFMA kernel (variant 1: the codebooks
+ * sit in LDS, each 16-token document tile is rebuilt from them into matrix
+ * operands and contracted with up to 8 x 16 query tokens per wave). Variant 1
+ * applies to F16 queries and codebooks with dsub in {8, 16, 32} and
+ * 16 * ceil(max_len / 16) * dim <= 1024 after rounding the block count up to
+ * a power of two; untuned keys use it whenever it applies. This call times
+ * both (synchronises `stream`) on the given problem, keeps the faster for the
+ * key (M, dsub, query blocks, candidates or not), rewrites cache_path (if not
+ * NULL) and writes a one-line JSON report. Workspace as for maxsim_pq_score
+ * with the table kernel (trials that need more are skipped).
+ */
+maxsim_status maxsim_pq_autotune(const maxsim_csr* queries, const maxsim_pq_docs* docs,
+                                 const maxsim_candidates* cand, float* scores, void* workspace,
+                                 size_t ws_bytes, maxsim_stream_t stream, int32_t reps,
+                                 const char* cache_path, char* report, size_t report_len);
 
 /*
  * Measured HBM read ceiling (for reporting the scorers against what the

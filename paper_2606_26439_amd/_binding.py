@@ -82,12 +82,15 @@ def lib():
     L.maxsim_autotune.argtypes = [_P(CSR), _P(CSR), _P(Cand), _vp, _vp, ctypes.c_size_t, _vp,
                                   ctypes.c_int32, ctypes.c_char_p, ctypes.c_char_p,
                                   ctypes.c_size_t]
+    L.maxsim_pq_autotune.argtypes = [_P(CSR), _P(PQ), _P(Cand), _vp, _vp, ctypes.c_size_t, _vp,
+                                     ctypes.c_int32, ctypes.c_char_p, ctypes.c_char_p,
+                                     ctypes.c_size_t]
     L.maxsim_load_tune_cache.argtypes = [ctypes.c_char_p]
     L.maxsim_stream_probe.argtypes = [_vp, ctypes.c_size_t, ctypes.c_int32, _vp, ctypes.c_int64,
                                       _vp]
     for name in ("maxsim_quantize", "maxsim_score", "maxsim_score_unfused", "maxsim_pq_score",
-                 "maxsim_topk", "maxsim_autotune", "maxsim_load_tune_cache",
-                 "maxsim_stream_probe"):
+                 "maxsim_topk", "maxsim_autotune", "maxsim_pq_autotune",
+                 "maxsim_load_tune_cache", "maxsim_stream_probe"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     # launch shapes tuned on an MI355X for the shipped key set (missing: defaults)
@@ -267,6 +270,25 @@ def autotune(q: Tokens, d: Tokens, cand: Candidates = None, reps: int = 10,
                                  ctypes.byref(cc) if cc is not None else None, _ptr(out), None, 0,
                                  _stream(stream), reps,
                                  cache_path.encode() if cache_path else None, buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
+def pq_autotune(q: Tokens, d: PQDocs, cand: Candidates = None, reps: int = 3,
+                cache_path: str = None, stream=None) -> dict:
+    """Times the table and decode-into-MFMA PQ scorers on this problem and
+    keeps the faster for its key."""
+    n = _n_pairs(q, d.n_docs, cand)
+    out = torch.empty(max(n, 1), dtype=torch.float32, device=d.offsets.device)
+    qc, pc = q.csr(), d.pq()
+    cc = cand.c() if cand is not None else None
+    ccp = ctypes.byref(cc) if cc is not None else None
+    need = int(lib().maxsim_pq_score_workspace_size(ctypes.byref(qc), ctypes.byref(pc), ccp))
+    # the table kernel's workspace (the decode kernel needs none)
+    ws = torch.empty(max(need, n * 4 * 8, 1), dtype=torch.uint8, device=d.offsets.device)
+    buf = ctypes.create_string_buffer(1 << 14)
+    _check(lib().maxsim_pq_autotune(ctypes.byref(qc), ctypes.byref(pc), ccp, _ptr(out), _ptr(ws),
+                                    ws.numel(), _stream(stream), reps,
+                                    cache_path.encode() if cache_path else None, buf, len(buf)))
     return json.loads(buf.value.decode())
 
 

@@ -22,9 +22,10 @@ ARCH = "gfx950"
 # element type so the four instantiation sets build in parallel.
 SOURCES = [("fused_inst.hip", f"fused_dt{t}", [f"-DFUSED_DT={t}"]) for t in range(4)] + [
     ("fused_dispatch.cpp", "fused_dispatch", []),
-    # NaN never reaches the PQ maxima (every table entry is a finite dot
-    # product), so the maxima need no NaN canonicalisation
+    # NaN never reaches the PQ maxima (every table entry and every decoded
+    # dot product is finite), so the maxima need no NaN canonicalisation
     ("pq.hip", "pq", ["-fno-honor-nans"]),
+    ("pq_mfma.hip", "pq_mfma", ["-fno-honor-nans"]),
     ("topk.hip", "topk", []),
     ("quantize.hip", "quantize", []),
     ("probe.hip", "probe", []),

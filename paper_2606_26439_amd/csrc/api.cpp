@@ -107,6 +107,20 @@ struct FusedCfg {
 std::mutex g_tune_mu;
 std::map<TuneKey, FusedCfg> g_tuned;
 
+// PQ scorer choice: the table kernel (variant 0) or decode-into-MFMA
+// (variant 1, with nqb query blocks per wave; 0 = automatic).
+struct PqKey {
+  int M, dsub, bpq, cand;
+  bool operator<(const PqKey& o) const {
+    return std::tie(M, dsub, bpq, cand) < std::tie(o.M, o.dsub, o.bpq, o.cand);
+  }
+};
+struct PqCfg {
+  int variant = -1;  // -1: automatic
+  int nqb = 0;
+};
+std::map<PqKey, PqCfg> g_pq_tuned;
+
 // Untuned keys: document tiles staged through LDS (the faster form measured on
 // MI355X for every element type but FP32) when the ring fits beside the query
 // block, else register-direct.
@@ -197,11 +211,24 @@ maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_
 
 maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s) {
   if (pl.n_pairs == 0) return MAXSIM_OK;
-  FusedFns fns = fused_kernel_fns(pl.dt, pl.nqb, pl.dch, cfg.pf, cfg.nw, pl.qreg, cfg.stage != 0);
   DevInfo di = device_info();
-  size_t lds = pl.lds;
-  if (cfg.stage) lds += (size_t)cfg.nw * cfg.pf * 16 * pl.dch * esize(pl.dt);
+  // query operand: VGPRs when d fits one chunk, else one LDS copy per wave
+  // when that fits beside the staging ring, else one per workgroup
+  const size_t ring = cfg.stage ? (size_t)cfg.nw * cfg.pf * 16 * pl.dch * esize(pl.dt) : 0;
+  int qm;
+  size_t lds;
+  if (pl.qreg) {
+    qm = 1;
+    lds = ring;
+  } else if ((size_t)cfg.nw * pl.lds + ring <= di.max_lds) {
+    qm = 2;
+    lds = (size_t)cfg.nw * pl.lds + ring;
+  } else {
+    qm = 0;
+    lds = pl.lds + ring;
+  }
   if (lds > di.max_lds) return fail(MAXSIM_EUNSUPPORTED, "staged tiles need %zu bytes of LDS", lds);
+  FusedFns fns = fused_kernel_fns(pl.dt, pl.nqb, pl.dch, cfg.pf, cfg.nw, qm, cfg.stage != 0);
   int occ = fns.occupancy(lds);
   if (occ <= 0) return fail(MAXSIM_EHIP, "fused kernel does not fit on a compute unit");
   int per_cu = cfg.wg_per_cu > 0 ? std::min(cfg.wg_per_cu, occ) : occ;
@@ -226,6 +253,16 @@ std::string cfg_json_all() {
              "\"stage\":%d}",
              first ? "" : ",", kv.first.dt, kv.first.dim, kv.first.nqb, kv.second.pf, kv.second.nw,
              kv.second.wg_per_cu, kv.second.stage);
+    out += b;
+    first = false;
+  }
+  for (auto& kv : g_pq_tuned) {
+    char b[192];
+    snprintf(b, sizeof b,
+             "%s{\"pq\":1,\"M\":%d,\"dsub\":%d,\"bpq\":%d,\"cand\":%d,\"variant\":%d,"
+             "\"nqb\":%d}",
+             first ? "" : ",", kv.first.M, kv.first.dsub, kv.first.bpq, kv.first.cand,
+             kv.second.variant, kv.second.nqb);
     out += b;
     first = false;
   }
@@ -283,7 +320,7 @@ maxsim_status maxsim_score(const maxsim_csr* queries, const maxsim_csr* docs,
   FusedPlan pl;
   maxsim_status st = plan_fused(queries, docs, cand, scores, pl);
   if (st) return st;
-  FusedCfg cfg = lookup_cfg({pl.dt, queries->dim, pl.nqb}, pl.lds, pl.dch);
+  FusedCfg cfg = lookup_cfg({pl.dt, queries->dim, pl.nqb}, pl.qreg ? 0 : pl.lds, pl.dch);
   return run_fused(pl, cfg, (hipStream_t)stream);
 }
 
@@ -319,10 +356,68 @@ struct PqPlan {
   PqParams P{};
   size_t lds = 0;
   size_t ws = 0;
+  int variant = 0;
 };
 
+int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+PqKey pq_key(const maxsim_csr* q, const maxsim_pq_docs* d, const maxsim_candidates* cand) {
+  return {d->M, d->dsub, pow2_at_least(std::max(1, (q->max_len + 15) / 16)), cand ? 1 : 0};
+}
+
+PqCfg lookup_pq(const PqKey& k) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_pq_tuned.find(k);
+  return it == g_pq_tuned.end() ? PqCfg{} : it->second;
+}
+
+// Decode-into-MFMA plan; returns false when the problem is outside what that
+// kernel handles (the table kernel is used then).
+bool plan_pq_mfma(const maxsim_csr* q, const maxsim_pq_docs* d, const maxsim_candidates* cand,
+                  int want_nqb, PqPlan& pl) {
+  if (q->dtype != MAXSIM_F16 || d->cb_dtype != MAXSIM_F16) return false;
+  if (d->dsub != 8 && d->dsub != 16 && d->dsub != 32) return false;
+  const size_t lds = (size_t)d->M * d->K * d->dsub * 2;
+  if (lds > device_info().max_lds) return false;
+  if (!aligned(d->codebooks, 16) || (q->n_tokens > 0 && !aligned(q->tokens, 16))) return false;
+  const int dim = d->M * d->dsub;
+  const int bpq = pow2_at_least(std::max(1, (q->max_len + 15) / 16));
+  if (bpq * dim > 1024) return false;  // query operand registers
+  int nqb = bpq;
+  if (!cand) {
+    const int cap = want_nqb > 0 ? want_nqb : 8;
+    nqb = 8;
+    while (nqb > bpq && (nqb > cap || nqb * dim > 1024)) nqb >>= 1;
+  } else if (want_nqb > 0 && want_nqb != bpq) {
+    return false;  // one query per group with candidate lists
+  }
+  PqParams& P = pl.P;
+  P.bpq = bpq;
+  P.nqb = nqb;
+  P.group = nqb / bpq;
+  P.nw = 8;
+  const int64_t n_groups = (q->n_sets + P.group - 1) / P.group;
+  const int64_t per_group_docs =
+      cand ? (q->n_sets > 0 ? cand->n_total / q->n_sets : 0) : d->n_docs;
+  // about eight resident workgroups per CU over the whole launch, chunks of
+  // at least 64 documents
+  const int64_t want = (int64_t)device_info().cus * 8;
+  int64_t n_chunks = std::max<int64_t>(1, (want + n_groups - 1) / std::max<int64_t>(1, n_groups));
+  n_chunks = std::min<int64_t>(n_chunks, std::max<int64_t>(1, per_group_docs / 64));
+  if (n_chunks * std::max<int64_t>(1, n_groups) > 0x7fffffffLL) return false;
+  P.n_chunks = (int)n_chunks;
+  pl.lds = lds;
+  pl.ws = 0;
+  pl.variant = 1;
+  return true;
+}
+
 maxsim_status plan_pq(const maxsim_csr* q, const maxsim_pq_docs* d, const maxsim_candidates* cand,
-                      float* scores, PqPlan& pl) {
+                      float* scores, PqPlan& pl, const PqCfg* force = nullptr) {
   if (!q || !d) return fail(MAXSIM_EINVAL, "pq: NULL descriptor");
   if (q->dtype != MAXSIM_F16 && q->dtype != MAXSIM_F32)
     return fail(MAXSIM_EUNSUPPORTED, "pq: queries must be F16 or F32");
@@ -378,6 +473,12 @@ maxsim_status plan_pq(const maxsim_csr* q, const maxsim_pq_docs* d, const maxsim
   P.dim = q->dim;
   P.qt = qt;
   P.n_slices = n_slices;
+  {
+    const PqCfg cfg = force ? *force : lookup_pq(pq_key(q, d, cand));
+    if (cfg.variant != 0 && plan_pq_mfma(q, d, cand, cfg.nqb, pl)) return MAXSIM_OK;
+    if (force && force->variant == 1)
+      return fail(MAXSIM_EUNSUPPORTED, "pq: decode-into-MFMA variant does not apply");
+  }
   // enough items to balance ~4 waves of workgroups over the CUs, but chunks
   // of at least ~512 pairs so the table build stays amortised
   int64_t base_items = std::max<int64_t>(1, q->n_sets * n_slices);
@@ -393,7 +494,12 @@ maxsim_status plan_pq(const maxsim_csr* q, const maxsim_pq_docs* d, const maxsim
   P.nw = 16;
   pl.lds = ((size_t)d->M * d->K * qt + (size_t)qt * q->dim) * 4;
   pl.ws = n_slices > 1 ? (size_t)n_slices * (size_t)n_pairs * 4 : 0;
+  pl.variant = 0;
   return MAXSIM_OK;
+}
+
+hipError_t run_pq(const PqPlan& pl, int max_len, hipStream_t s) {
+  return pl.variant == 1 ? launch_pq_mfma(pl.P, pl.lds, s) : launch_pq(pl.P, max_len, s);
 }
 }  // namespace
 
@@ -418,8 +524,80 @@ maxsim_status maxsim_pq_score(const maxsim_csr* queries, const maxsim_pq_docs* d
     return fail(MAXSIM_EWORKSPACE, "pq: workspace needs %zu bytes", pl.ws);
   if (pl.P.n_pairs == 0) return MAXSIM_OK;
   pl.P.partial = (float*)workspace;
-  hipError_t e = launch_pq(pl.P, queries->max_len, (hipStream_t)stream);
+  hipError_t e = run_pq(pl, queries->max_len, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "pq launch");
+  return MAXSIM_OK;
+}
+
+maxsim_status maxsim_pq_autotune(const maxsim_csr* queries, const maxsim_pq_docs* docs,
+                                 const maxsim_candidates* cand, float* scores, void* workspace,
+                                 size_t ws_bytes, maxsim_stream_t stream, int32_t reps,
+                                 const char* cache_path, char* report, size_t report_len) {
+  PqPlan probe;
+  maxsim_status st = plan_pq(queries, docs, cand, scores, probe);
+  if (st) return st;
+  if (reps < 1) reps = 1;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(MAXSIM_EHIP, "pq autotune: event creation failed");
+  std::vector<PqCfg> space;
+  space.push_back({0, 0});
+  for (int nqb : {1, 2, 4, 8}) space.push_back({1, nqb});
+  const PqKey key = pq_key(queries, docs, cand);
+  std::string rep = "{\"pq\":1,\"M\":" + std::to_string(key.M) + ",\"dsub\":" +
+                    std::to_string(key.dsub) + ",\"bpq\":" + std::to_string(key.bpq) +
+                    ",\"cand\":" + std::to_string(key.cand) + ",\"trials\":[";
+  float best_ms = 1e30f;
+  PqCfg best{0, 0};
+  bool first = true;
+  for (const PqCfg& c : space) {
+    PqPlan pl;
+    if (plan_pq(queries, docs, cand, scores, pl, &c)) continue;  // does not apply
+    if (c.variant == 1 && pl.P.nqb != c.nqb) continue;          // same shape as another trial
+    if (pl.ws > 0 && (!workspace || ws_bytes < pl.ws)) continue;
+    pl.P.partial = (float*)workspace;
+    if (pl.P.n_pairs == 0) break;
+    if (run_pq(pl, queries->max_len, s) != hipSuccess) continue;
+    (void)hipEventRecord(e0, s);
+    bool ok = true;
+    for (int r = 0; r < reps && ok; ++r) ok = run_pq(pl, queries->max_len, s) == hipSuccess;
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess || !ok) continue;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= reps;
+    char b[128];
+    snprintf(b, sizeof b, "%s{\"variant\":%d,\"nqb\":%d,\"ms\":%.5f}", first ? "" : ",",
+             c.variant, c.variant ? pl.P.nqb : 0, ms);
+    rep += b;
+    first = false;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = {c.variant, c.variant ? pl.P.nqb : 0};
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  char b[128];
+  snprintf(b, sizeof b, "],\"best\":{\"variant\":%d,\"nqb\":%d,\"ms\":%.5f}}", best.variant,
+           best.nqb, best_ms);
+  rep += b;
+  std::string all;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_pq_tuned[key] = best;
+    all = cfg_json_all();
+  }
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "wb");
+    if (!f) return fail(MAXSIM_EINVAL, "pq autotune: cannot write %s", cache_path);
+    fputs(all.c_str(), f);
+    fclose(f);
+  }
+  if (report && report_len > 0) {
+    snprintf(report, report_len, "%s", rep.c_str());
+  }
   return MAXSIM_OK;
 }
 
@@ -490,6 +668,20 @@ maxsim_status maxsim_load_tune_cache(const char* path) {
     }
     pos = end;
   }
+  pos = 0;
+  while ((pos = txt.find("{\"pq\"", pos)) != std::string::npos) {
+    size_t end = txt.find('}', pos);
+    if (end == std::string::npos) break;
+    std::string obj = txt.substr(pos, end - pos + 1);
+    PqKey k{};
+    PqCfg c{};
+    if (json_int(obj.c_str(), "M", k.M) && json_int(obj.c_str(), "dsub", k.dsub) &&
+        json_int(obj.c_str(), "bpq", k.bpq) && json_int(obj.c_str(), "cand", k.cand) &&
+        json_int(obj.c_str(), "variant", c.variant) && json_int(obj.c_str(), "nqb", c.nqb)) {
+      if ((c.variant == 0 || c.variant == 1) && (c.nqb >= 0 && c.nqb <= 8)) g_pq_tuned[k] = c;
+    }
+    pos = end;
+  }
   return MAXSIM_OK;
 }
 
@@ -523,7 +715,7 @@ maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
                     std::to_string(queries->dim) + ",\"nqb\":" + std::to_string(pl.nqb) +
                     ",\"trials\":[";
   float best_ms = 1e30f;
-  FusedCfg best = default_cfg(pl.dt, pl.lds, pl.dch);
+  FusedCfg best = default_cfg(pl.dt, pl.qreg ? 0 : pl.lds, pl.dch);
   bool first = true;
   for (const FusedCfg& c : space) {
     if (run_fused(pl, c, s)) continue;  // warm-up (also skips shapes that do not fit)

@@ -97,16 +97,17 @@ __device__ __forceinline__ f32x4 mma_step(f32x4 acc, const u32x4 (&a)[NL], const
   return acc;
 }
 
-// Stage query `a` into LDS in the B-operand layout. Returns Nq (host-trusted
-// capacity is checked by the caller).
+// Stage query `a` into LDS in the B-operand layout, threads t0, t0 + nthreads,
+// ... of the caller's group doing the copy. Returns Nq (host-trusted capacity
+// is checked by the caller).
 template <int NQB>
-__device__ int stage_query(const FusedParams& P, int64_t a, u32x4* q_lds, int nthreads) {
+__device__ int stage_query(const FusedParams& P, int64_t a, u32x4* q_lds, int t0, int nthreads) {
   const int64_t q0 = P.q_off[a];
   const int nq = (int)(P.q_off[a + 1] - q0);
   const int ncg = P.row_bytes / 64;  // 16-byte column groups per lane-group row
   const int total = NQB * ncg * 64;
   const char* qbase = P.q_tok + q0 * P.row_bytes;
-  for (int idx = threadIdx.x; idx < total; idx += nthreads) {
+  for (int idx = t0; idx < total; idx += nthreads) {
     int ln = idx & 63, rest = idx >> 6;
     int cg = rest % ncg, nb = rest / ncg;
     int row = nb * 16 + (ln & 15);
@@ -128,9 +129,20 @@ constexpr size_t stage_ring_bytes() {
 // (vmcnt in bits 3:0 and 15:14; expcnt and lgkmcnt left at their maxima).
 constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8); }
 
-template <int DT, int NQB, int DCH, int PF, int NW, bool QREG, bool STAGE>
+// Where a wave's query operand lives (QM):
+//   Q_SHARED  one LDS copy per workgroup (large d); the workgroup's waves
+//             stage each query they cross together, with barriers;
+//   Q_REGS    VGPRs, loaded by each wave itself (d fits one chunk);
+//   Q_WAVE    one LDS copy per wave, staged by that wave alone.
+// The per-wave forms need no barrier, so a wave never waits for the others
+// when their ranges cross different queries.
+constexpr int Q_SHARED = 0, Q_REGS = 1, Q_WAVE = 2;
+
+template <int DT, int NQB, int DCH, int PF, int NW, int QM, bool STAGE>
 __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
   extern __shared__ u32x4 q_lds[];
+  constexpr bool QREG = QM == Q_REGS;
+  constexpr bool PERWAVE = QM != Q_SHARED;
   constexpr int ESZ = elem_size<DT>::value;
   constexpr int CB = DCH * ESZ;  // bytes of one row within one chunk
   constexpr int NL = CB / 64;    // 16-byte loads per lane per step
@@ -157,8 +169,12 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
   const int64_t wg0 = (int64_t)blockIdx.x * NW;
   const int64_t my_lo = uniform64(wave_range_begin(P, wg0 + wave, W));
   const int64_t my_hi = uniform64(wave_range_begin(P, wg0 + wave + 1, W));
-  int64_t pb = uniform64(wave_range_begin(P, wg0, W));
-  const int64_t pe = uniform64(wave_range_begin(P, wg0 + NW, W));
+  // segments: the query-sized pieces of the workgroup's range (shared Q) or
+  // of this wave's own range (per-wave Q)
+  int64_t pb = PERWAVE ? my_lo : uniform64(wave_range_begin(P, wg0, W));
+  const int64_t pe = PERWAVE ? my_hi : uniform64(wave_range_begin(P, wg0 + NW, W));
+  // this wave's query operand in LDS (shared: the workgroup's copy)
+  u32x4* qw = q_lds + (QM == Q_WAVE ? (size_t)wave * NQB * ncg * 64 : 0);
 
   while (pb < pe) {
     int64_t a, qend;
@@ -170,9 +186,22 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       qend = P.cand_off[a + 1];
     }
     const int64_t se = qend < pe ? qend : pe;
-    __syncthreads();
-    const int nq = uniform(stage_query<NQB>(P, a, q_lds, NW * 64));
-    __syncthreads();
+    int nq;
+    if constexpr (QM == Q_SHARED) {
+      __syncthreads();
+      nq = uniform(stage_query<NQB>(P, a, q_lds, threadIdx.x, NW * 64));
+      __syncthreads();
+    } else if constexpr (QM == Q_WAVE) {
+      // the wave's own LDS ops complete in order; the fence keeps the
+      // compiler from moving the operand reads above the staging writes
+      __builtin_amdgcn_wave_barrier();
+      nq = uniform(stage_query<NQB>(P, a, qw, lane, 64));
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      nq = uniform((int)(P.q_off[a + 1] - P.q_off[a]));
+    }
 
     int64_t lo = my_lo > pb ? my_lo : pb;
     const int64_t hi = my_hi < se ? my_hi : se;
@@ -184,13 +213,21 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       continue;
     }
 
-    // Query operand registers (one d-chunk) and FP8 query scales.
+    // Query operand registers (one d-chunk, loaded by the wave itself) and
+    // FP8 query scales.
     u32x4 qreg[QREG ? NQB : 1][NL];
     if constexpr (QREG) {
+      const char* qbase = P.q_tok + P.q_off[a] * P.row_bytes + g * 16;
 #pragma unroll
-      for (int nb = 0; nb < NQB; ++nb)
+      for (int nb = 0; nb < NQB; ++nb) {
+        const int row = nb * 16 + r;
 #pragma unroll
-        for (int c = 0; c < NL; ++c) qreg[nb][c] = q_lds[(nb * ncg + c) * 64 + lane];
+        for (int c = 0; c < NL; ++c) {
+          u32x4 v = {0u, 0u, 0u, 0u};
+          if (row < nq) v = *(const u32x4*)(qbase + (int64_t)row * P.row_bytes + c * 64);
+          qreg[nb][c] = v;
+        }
+      }
     }
     int qsc[NQB];
 #pragma unroll
@@ -248,7 +285,8 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     int bsc[PF];
     int flags[PF];
     int64_t fp[PF];
-    char* ring = (char*)q_lds + (size_t)NQB * 16 * P.row_bytes + (size_t)wave * PF * TILE;
+    constexpr int Q_COPIES = QM == Q_SHARED ? 1 : (QM == Q_WAVE ? NW : 0);
+    char* ring = (char*)q_lds + (size_t)Q_COPIES * NQB * 16 * P.row_bytes + (size_t)wave * PF * TILE;
     auto swz = [](int row) { return (row / SWD) & (SW - 1); };
 
     // Every fill issues exactly NL (+1 for FP8) loads, from a harmless address
@@ -375,7 +413,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
         for (int nb = 0; nb < NQB; ++nb) {
           u32x4 qb[NL];
 #pragma unroll
-          for (int c = 0; c < NL; ++c) qb[c] = q_lds[(nb * ncg + chunk * NL + c) * 64 + lane];
+          for (int c = 0; c < NL; ++c) qb[c] = qw[(nb * ncg + chunk * NL + c) * 64 + lane];
           f32x4 base = first ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[nb];
           acc[nb] = mma_step<DT, NL>(base, bb, qb, sc, qsc[nb]);
         }
@@ -432,7 +470,7 @@ __global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, floa
   const int64_t ntiles = (T + 15) / 16;
   const int ncg = P.row_bytes / 64;
 
-  const int nq = uniform(stage_query<NQB>(P, a, q_lds, NW * 64));
+  const int nq = uniform(stage_query<NQB>(P, a, q_lds, threadIdx.x, NW * 64));
   __syncthreads();
   int qsc[NQB];
 #pragma unroll

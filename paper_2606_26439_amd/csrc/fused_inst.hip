@@ -11,9 +11,9 @@ namespace {
 
 constexpr int DT = FUSED_DT;
 
-template <int NQB, int DCH, int PF, int NW, bool QREG, bool STAGE>
+template <int NQB, int DCH, int PF, int NW, int QM, bool STAGE>
 hipError_t launch_fused_t(const FusedParams& P, int grid, size_t lds, hipStream_t s) {
-  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QREG, STAGE>;
+  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QM, STAGE>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
@@ -23,9 +23,9 @@ hipError_t launch_fused_t(const FusedParams& P, int grid, size_t lds, hipStream_
   return hipGetLastError();
 }
 
-template <int NQB, int DCH, int PF, int NW, bool QREG, bool STAGE>
+template <int NQB, int DCH, int PF, int NW, int QM, bool STAGE>
 int occupancy_fused_t(size_t lds) {
-  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QREG, STAGE>;
+  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QM, STAGE>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
           hipSuccess)
@@ -36,35 +36,38 @@ int occupancy_fused_t(size_t lds) {
 }
 
 template <int NQB, int DCH, int PF, int NW, bool STAGE>
-FusedFns pick_q(bool qreg) {
-  if (qreg)
-    return {launch_fused_t<NQB, DCH, PF, NW, true, STAGE>,
-            occupancy_fused_t<NQB, DCH, PF, NW, true, STAGE>, STAGE};
-  return {launch_fused_t<NQB, DCH, PF, NW, false, STAGE>,
-          occupancy_fused_t<NQB, DCH, PF, NW, false, STAGE>, STAGE};
+FusedFns pick_q(int qm) {
+  if (qm == fused_detail::Q_REGS)
+    return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE>,
+            occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE>, STAGE};
+  if (qm == fused_detail::Q_WAVE)
+    return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_WAVE, STAGE>,
+            occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_WAVE, STAGE>, STAGE};
+  return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_SHARED, STAGE>,
+          occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_SHARED, STAGE>, STAGE};
 }
 
 template <int NQB, int DCH, int PF, bool STAGE>
-FusedFns pick_nw(int nw, bool qreg) {
-  return nw == 8 ? pick_q<NQB, DCH, PF, 8, STAGE>(qreg) : pick_q<NQB, DCH, PF, 4, STAGE>(qreg);
+FusedFns pick_nw(int nw, int qm) {
+  return nw == 8 ? pick_q<NQB, DCH, PF, 8, STAGE>(qm) : pick_q<NQB, DCH, PF, 4, STAGE>(qm);
 }
 
 template <int NQB, int DCH, bool STAGE>
-FusedFns pick_pf(int pf, int nw, bool qreg) {
-  if (pf == 2) return pick_nw<NQB, DCH, 2, STAGE>(nw, qreg);
-  if (pf == 3) return pick_nw<NQB, DCH, 3, STAGE>(nw, qreg);
-  return pick_nw<NQB, DCH, 4, STAGE>(nw, qreg);
+FusedFns pick_pf(int pf, int nw, int qm) {
+  if (pf == 2) return pick_nw<NQB, DCH, 2, STAGE>(nw, qm);
+  if (pf == 3) return pick_nw<NQB, DCH, 3, STAGE>(nw, qm);
+  return pick_nw<NQB, DCH, 4, STAGE>(nw, qm);
 }
 
 template <int NQB, int DCH>
-FusedFns pick_stage(int pf, int nw, bool qreg, bool stage) {
-  return stage ? pick_pf<NQB, DCH, true>(pf, nw, qreg) : pick_pf<NQB, DCH, false>(pf, nw, qreg);
+FusedFns pick_stage(int pf, int nw, int qm, bool stage) {
+  return stage ? pick_pf<NQB, DCH, true>(pf, nw, qm) : pick_pf<NQB, DCH, false>(pf, nw, qm);
 }
 
 template <int NQB>
-FusedFns pick_dch(int dch, int pf, int nw, bool qreg, bool stage) {
-  return dch == 64 ? pick_stage<NQB, 64>(pf, nw, qreg, stage)
-                   : pick_stage<NQB, 128>(pf, nw, qreg, stage);
+FusedFns pick_dch(int dch, int pf, int nw, int qm, bool stage) {
+  return dch == 64 ? pick_stage<NQB, 64>(pf, nw, qm, stage)
+                   : pick_stage<NQB, 128>(pf, nw, qm, stage);
 }
 
 template <int NQB, int DCH>
@@ -99,11 +102,11 @@ hipError_t unfused_dch(const FusedParams& P, float* S, int grid, size_t lds, int
 #define CAT2(a, b) a##b
 #define CAT(a, b) CAT2(a, b)
 
-FusedFns CAT(fused_kernel_fns_, FUSED_DT)(int nqb, int dch, int pf, int nw, bool qreg,
+FusedFns CAT(fused_kernel_fns_, FUSED_DT)(int nqb, int dch, int pf, int nw, int qm,
                                            bool stage) {
-  if (nqb == 1) return pick_dch<1>(dch, pf, nw, qreg, stage);
-  if (nqb == 2) return pick_dch<2>(dch, pf, nw, qreg, stage);
-  return pick_dch<4>(dch, pf, nw, qreg, stage);
+  if (nqb == 1) return pick_dch<1>(dch, pf, nw, qm, stage);
+  if (nqb == 2) return pick_dch<2>(dch, pf, nw, qm, stage);
+  return pick_dch<4>(dch, pf, nw, qm, stage);
 }
 
 hipError_t CAT(launch_unfused_, FUSED_DT)(int nqb, int dch, const FusedParams& P, float* S,

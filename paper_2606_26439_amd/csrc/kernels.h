@@ -36,10 +36,12 @@ struct FusedFns {
 };
 
 // dt: maxsim_dtype; nqb: query blocks of 16 (1, 2, 4); dch: 64 or 128;
-// pf: prefetch depth (2, 3, 4); nw: waves per workgroup (4, 8); qreg: Q in VGPRs;
+// pf: prefetch depth (2, 3, 4); nw: waves per workgroup (4, 8); qm: where the
+// query operand lives (0: one LDS copy per workgroup, 1: VGPRs, d in one
+// chunk; 2: one LDS copy per wave);
 // stage: document tiles arrive through a per-wave LDS ring (pf slots of
 // 16 rows x dch elements per wave, after the query block) instead of VGPRs.
-FusedFns fused_kernel_fns(int dt, int nqb, int dch, int pf, int nw, bool qreg, bool stage);
+FusedFns fused_kernel_fns(int dt, int nqb, int dch, int pf, int nw, int qm, bool stage);
 
 hipError_t launch_unfused(int dt, int nqb, int dch, const FusedParams& P, float* S, int grid,
                           size_t lds, hipStream_t s);
@@ -64,10 +66,18 @@ struct PqParams {
   int32_t M, K, dsub, dim;
   int32_t qt;        // query tokens per slice (LUT rows)
   int32_t n_slices;  // ceil(max Nq / qt)
-  int32_t n_chunks;  // doc-range chunks per (query, slice)
+  int32_t n_chunks;  // doc-range chunks per (query, slice) or per query group
   int32_t nw;        // waves per workgroup (8 or 16)
+  // decode-into-MFMA variant only
+  int32_t bpq;    // 16-column query blocks per query (ceil(max Nq / 16))
+  int32_t group;  // queries per work item
+  int32_t nqb;    // query blocks per wave (group * bpq)
+  int32_t pad;
 };
 hipError_t launch_pq(const PqParams& P, int max_nq, hipStream_t s);
+// Decode-into-MFMA PQ scorer: F16 queries and codebooks, dsub in {8, 16, 32};
+// lds = M * K * dsub * 2 bytes; nqb in {1, 2, 4, 8} with nqb * M * dsub <= 1024.
+hipError_t launch_pq_mfma(const PqParams& P, size_t lds, hipStream_t s);
 
 // ---- top-k ----
 hipError_t launch_topk(const float* scores, const int64_t* seg_off, int64_t n_seg, int64_t n_total,

@@ -178,7 +178,16 @@ def test_every_launch_configuration_is_bit_identical(tmp_path, dtype, dim):
             for pf in (2, 3, 4):
                 for nw in (4, 8):
                     _force_cfg(tmp_path, dtype, dim, stage, pf, nw)
-                    lds = 4 * 16 * dim * esz + stage * nw * pf * 16 * dch * esz
+                    # query operand: VGPRs (one chunk), per-wave LDS copies
+                    # if they fit beside the ring, else one shared copy
+                    q1 = 4 * 16 * dim * esz
+                    ring = stage * nw * pf * 16 * dch * esz
+                    if dim == dch:
+                        lds = ring
+                    elif nw * q1 + ring <= 160 * 1024:
+                        lds = nw * q1 + ring
+                    else:
+                        lds = q1 + ring
                     if lds > 160 * 1024:
                         with pytest.raises(M.MaxSimError):
                             M.score(Q, D)
@@ -274,7 +283,31 @@ def _pq_device(q, q_off, cb, codes, d_off):
     return Q, D
 
 
-def test_pq_integer_table_is_bit_exact():
+PQ_VARIANTS = ["table", "mfma"]
+
+
+@pytest.fixture
+def pq_variant(request, tmp_path):
+    """Forces the PQ scorer (table kernel or decode-into-MFMA) for every key
+    the test can touch; afterwards restores the automatic choice."""
+    v = 0 if request.param == "table" else 1
+
+    def write(variant):
+        entries = [{"pq": 1, "M": m, "dsub": ds, "bpq": b, "cand": c, "variant": variant, "nqb": 0}
+                   for m in (4, 8, 16) for ds in (4, 8, 16, 32) for b in (1, 2, 4) for c in (0, 1)]
+        path = tmp_path / f"pq_{variant}.json"
+        path.write_text(json.dumps({"version": 1, "entries": entries}))
+        M.load_tune_cache(str(path))
+
+    write(v)
+    yield request.param
+    write(1)  # variant 1 where it applies, else the table kernel: the default
+    M.load_tune_cache(M.default_tune_cache())
+
+
+@pytest.mark.parametrize("pq_variant", PQ_VARIANTS, indirect=True)
+def test_pq_integer_table_is_bit_exact(pq_variant):
+    # small integers: every product and sum is exact in FP32 on both kernels
     q, q_off, cb, codes, d_off = _pq_case(200, 8, 256, 16, seed=1, nq_lens=[32, 5], integer=True)
     Q, D = _pq_device(q, q_off, cb, codes, d_off)
     got = M.pq_score(Q, D).cpu().numpy()
@@ -282,21 +315,48 @@ def test_pq_integer_table_is_bit_exact():
     assert np.array_equal(got.astype(np.float64), want)
 
 
-@pytest.mark.parametrize("shape", [(8, 256, 16), (16, 256, 8), (4, 64, 32)])
-def test_pq_matches_decode_then_score(shape):
+@pytest.mark.parametrize("pq_variant", PQ_VARIANTS, indirect=True)
+@pytest.mark.parametrize("shape", [(8, 256, 16), (16, 256, 8), (4, 64, 32), (8, 256, 32),
+                                   (16, 16, 4)])
+def test_pq_matches_decode_then_score(pq_variant, shape):
     M_, K, dsub = shape
     q, q_off, cb, codes, d_off = _pq_case(300, M_, K, dsub, seed=M_ + K, nq_lens=[32, 64, 3])
     Q, D = _pq_device(q, q_off, cb, codes, d_off)
     got = M.pq_score(Q, D).cpu().numpy()
     want = oracle.pq_decode_score(q.astype(np.float64), q_off, codes, cb.astype(np.float64), d_off)
-    assert_close_o1(got, want, f"pq {shape}")
+    assert_close_o1(got, want, f"pq {shape} {pq_variant}")
 
 
-def test_pq_candidates():
+@pytest.mark.parametrize("pq_variant", PQ_VARIANTS, indirect=True)
+def test_pq_many_queries_grouped(pq_variant):
+    # 11 queries of uneven length (one empty) against ragged docs (one
+    # empty): the decode kernel packs several queries per wave
+    nq_lens = [32, 5, 0, 17, 32, 1, 30, 32, 8, 32, 31]
+    q, q_off, cb, codes, d_off = _pq_case(260, 8, 256, 16, seed=23, nq_lens=nq_lens)
+    Q, D = _pq_device(q, q_off, cb, codes, d_off)
+    got = M.pq_score(Q, D).cpu().numpy()
+    want = oracle.pq_decode_score(q.astype(np.float64), q_off, codes, cb.astype(np.float64), d_off)
+    assert_close_o1(got, want, f"pq grouped {pq_variant}")
+
+
+@pytest.mark.parametrize("pq_variant", PQ_VARIANTS, indirect=True)
+def test_pq_candidates(pq_variant):
     q, q_off, cb, codes, d_off = _pq_case(500, 8, 256, 16, seed=7, nq_lens=[32, 16, 50])
     cand_off, cand_ids = W.candidates(3, 500, seed=8, size_range=(50, 400))
     Q, D = _pq_device(q, q_off, cb, codes, d_off)
     got = M.pq_score(Q, D, M.Candidates(dev(cand_off), dev(cand_ids))).cpu().numpy()
     want = oracle.pq_decode_score(q.astype(np.float64), q_off, codes, cb.astype(np.float64), d_off,
                                   cand_off, cand_ids)
-    assert_close_o1(got, want, "pq candidates")
+    assert_close_o1(got, want, f"pq candidates {pq_variant}")
+
+
+def test_pq_autotune_keeps_results_within_tolerance(tmp_path):
+    q, q_off, cb, codes, d_off = _pq_case(400, 8, 256, 16, seed=29, nq_lens=[32] * 9)
+    Q, D = _pq_device(q, q_off, cb, codes, d_off)
+    rep = M.pq_autotune(Q, D, reps=2)
+    assert {t["variant"] for t in rep["trials"]} == {0, 1}, rep
+    assert rep["best"]["ms"] > 0
+    got = M.pq_score(Q, D).cpu().numpy()
+    want = oracle.pq_decode_score(q.astype(np.float64), q_off, codes, cb.astype(np.float64), d_off)
+    assert_close_o1(got, want, "pq after autotune")
+    M.load_tune_cache(M.default_tune_cache())

@@ -88,3 +88,52 @@ def test_served_topk_matches_oracle(pool):
         # and the returned scores match the oracle's scores of those docs
         np.testing.assert_allclose(r.top_scores[:k].astype(np.float64),
                                    [by_id[i] for i in got], rtol=1e-5, atol=1e-5)
+
+
+def test_full_5m_pool_requests_match_oracle():
+    # The serving pool at full size (5M FP16 docs, 88.8 GB, plus the PQ copy);
+    # a few requests with small candidate sets so the oracle scores every one.
+    from tests._gpu import doc_rows, gen_device_tokens
+    n_pool, k = 5_000_000, 100
+    lens = W.doc_lengths(n_pool, 0)
+    d_off = W.offsets_from_lengths(lens)
+    T = int(d_off[-1])
+    g = W.rng(21)
+    cands = [np.sort(g.choice(n_pool, int(n), replace=False)).astype(np.int32)
+             for n in (150, 1200, 2500, 2500)]
+    rows_all, _ = doc_rows(d_off, np.unique(np.concatenate(cands)))
+    tok, _, f32 = gen_device_tokens(T, 128, "f16", seed=5000, sample_rows=rows_all)
+    d_off_dev = dev(d_off)
+    docs = M.Tokens(tok, d_off_dev, "f16", None, max_len=int(lens.max()))
+    codes = W.pq_codes_gpu(T, 8, 256, seed=2)
+    cb = W.pq_codebooks(8, 256, 16, seed=2)
+    pq = M.PQDocs(dev(cb), codes, d_off_dev)
+    reqs = [S.Request(i, W.unit_tokens(int(g.integers(8, 65)), 128, g), c,
+                      mode="pq" if i % 2 else "exact") for i, c in enumerate(cands)]
+    be = S.GpuBackend(docs, pq, k=k)
+    S.Server(S.Scheduler(128, k), be).run(reqs)
+    # position of each pool row inside the gathered FP32 sample
+    where = {int(r): i for i, r in enumerate(rows_all)}
+    cb64 = cb.astype(np.float64)
+    for r in reqs:
+        assert r.status == "done", (r.rid, r.status, r.error)
+        rows, off = doc_rows(d_off, r.cand_ids)
+        qv, _ = oracle.exact_values(r.query, "f16")
+        nq = len(qv)
+        if r.mode == "pq":
+            c = codes[torch.from_numpy(rows).cuda()].cpu().numpy()
+            want = oracle.pq_decode_score(qv, [0, nq], c, cb64, off)
+        else:
+            dv, _ = oracle.exact_values(f32[[where[int(x)] for x in rows]], "f16")
+            want = oracle.maxsim(qv, [0, nq], dv, off)
+        kk = min(k, len(want))
+        ex_ids, ex_s = oracle.topk(want, kk, r.cand_ids.astype(np.int64))
+        by_id = dict(zip(r.cand_ids.tolist(), want.tolist()))
+        got = r.top_ids[:kk].tolist()
+        kth = float(ex_s[kk - 1])
+        for i in set(got) ^ set(ex_ids.tolist()):  # only near-ties may differ
+            assert abs(by_id[i] - kth) <= 1e-5 * 64, (r.rid, i)
+        np.testing.assert_allclose(r.top_scores[:kk].astype(np.float64),
+                                   [by_id[i] for i in got], rtol=1e-5, atol=1e-5)
+    del tok, docs, codes, pq, be
+    torch.cuda.empty_cache()
