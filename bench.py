@@ -329,9 +329,12 @@ def bench_pq(n_docs=2_000_000, n_queries=64, nq=32, M_=8, K=256, dsub=16):
     return rec
 
 
-def bench_serving(n_pool=5_000_000, qps_levels=(1000, 4000, 8000, 16000), n_req=2000, k=100,
-                  pq_qps=4000):
-    """5M-doc FP16 pool + PQ copy; open-loop Poisson arrivals; top-100."""
+def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_000, k=100,
+                  n_sets=2048, n_sat=1500):
+    """5M-doc FP16 pool + PQ copy; top-100. Per mode, the saturation rate is
+    measured first (every request queued at once), then open-loop Poisson
+    arrivals run at fixed fractions of it, n_req requests per level. Requests
+    cycle through n_sets seeded (query, candidate set) pairs."""
     import torch
     import paper_2606_26439_amd as M
     import workloads as W
@@ -348,53 +351,69 @@ def bench_serving(n_pool=5_000_000, qps_levels=(1000, 4000, 8000, 16000), n_req=
     log(f"[bench] serving pool: {n_pool} docs, {T} tokens, "
         f"{tok.numel() * 2 / 1e9:.1f} GB FP16 + {codes.numel() / 1e9:.2f} GB codes, "
         f"built in {time.time() - t0:.1f}s")
-    n_all = n_req * (len(qps_levels) + 1) + 16
     g = W.rng(1)
-    nqs = g.integers(8, 65, size=n_all)
+    nqs = g.integers(8, 65, size=n_sets)
     queries = [W.unit_tokens(int(n), 128, g) for n in nqs]
-    c_off, c_ids = W.candidates(n_all, n_pool, seed=4)
+    c_off, c_ids = W.candidates(n_sets, n_pool, seed=4)
+    counter = [0]
 
-    def mk(i, mode):
-        return S.Request(i, queries[i], c_ids[c_off[i]:c_off[i + 1]], mode=mode)
+    def mk(mode):
+        i = counter[0]
+        counter[0] += 1
+        j = i % n_sets
+        return S.Request(i, queries[j], c_ids[c_off[j]:c_off[j + 1]], mode=mode)
 
     backend = S.GpuBackend(pool, pq, k=k, n_slots=3)
     # warm-up: grow every slot's buffers to a large batch and touch both modes
-    warm = [mk(n_all - 1 - j, "exact" if j % 2 else "pq") for j in range(16)]
-    S.Server(S.Scheduler(128, k, max_inflight=3), backend).run(warm)
+    S.Server(S.Scheduler(128, k, max_inflight=3), backend).run(
+        [mk("exact" if j % 2 else "pq") for j in range(16)])
     import gc
     gc.collect()
-    gc.disable()  # no collector pauses inside the timed open-loop runs
-    results = []
-    base = 0
-    levels = [(q, "exact") for q in qps_levels] + [(pq_qps, "pq")]
-    for qps, mode in levels:
-        reqs = [mk(base + i, mode) for i in range(n_req)]
-        base += n_req
-        arr = W.poisson_arrivals(n_req, qps, seed=3)
+    gc.disable()  # no collector pauses inside the timed runs
+
+    def run(reqs, arrivals):
         sched = S.Scheduler(128, k, max_inflight=3, mem_budget=8 << 30)
         srv = S.Server(sched, backend)
         start = time.perf_counter() + 0.01
-        for r, a in zip(reqs, arr):
+        for r, a in zip(reqs, arrivals):
             r.arrival = start + float(a)
         torch.cuda.synchronize()
         done = srv.run(reqs)
         wall = max(r.done_at for r in done) - start
-        scored = sum(len(r.cand_ids) for r in done if r.status == "done")
-        st = S.latency_stats(done)
-        rec = {"mode": mode, "qps_offered": qps, "n_requests": n_req,
-               "qps_achieved": len(done) / wall, "docs_per_s": scored / wall,
-               "batches": srv.batches_launched, "mean_batch": n_req / max(1, srv.batches_launched),
-               "max_queue_depth": srv.max_queue_depth,
-               "statuses": {s_: sum(r.status == s_ for r in done) for s_ in {r.status for r in done}},
-               **st}
-        log(f"[bench] serving {mode} @ {qps} QPS: p50 {st.get('p50_ms', 0):.2f} ms, "
-            f"p99 {st.get('p99_ms', 0):.2f} ms, {rec['docs_per_s'] / 1e6:.1f} M docs/s, "
-            f"mean batch {rec['mean_batch']:.1f}")
-        results.append(rec)
+        return srv, done, wall
+
+    results, saturation = [], {}
+    for mode in ("exact", "pq"):
+        reqs = [mk(mode) for _ in range(n_sat)]
+        srv, done, wall = run(reqs, np.zeros(n_sat))
+        sat = len(done) / wall
+        saturation[mode] = {"qps": sat, "docs_per_s": sum(len(r.cand_ids) for r in done) / wall,
+                            "mean_batch": n_sat / max(1, srv.batches_launched)}
+        log(f"[bench] serving {mode}: saturation {sat:.0f} QPS, "
+            f"{saturation[mode]['docs_per_s'] / 1e6:.1f} M docs/s")
+        for fr in fractions:
+            qps = fr * sat
+            reqs = [mk(mode) for _ in range(n_req)]
+            srv, done, wall = run(reqs, W.poisson_arrivals(n_req, qps, seed=3))
+            scored = sum(len(r.cand_ids) for r in done if r.status == "done")
+            st = S.latency_stats(done)
+            rec = {"mode": mode, "fraction_of_saturation": fr, "qps_offered": qps,
+                   "n_requests": n_req, "qps_achieved": len(done) / wall,
+                   "docs_per_s": scored / wall, "batches": srv.batches_launched,
+                   "mean_batch": n_req / max(1, srv.batches_launched),
+                   "max_queue_depth": srv.max_queue_depth,
+                   "statuses": {s_: sum(r.status == s_ for r in done)
+                                for s_ in {r.status for r in done}},
+                   **st}
+            log(f"[bench] serving {mode} @ {qps:.0f} QPS ({fr:.2f} of saturation): "
+                f"p50 {st.get('p50_ms', 0):.2f} ms, p99 {st.get('p99_ms', 0):.2f} ms, "
+                f"{rec['docs_per_s'] / 1e6:.1f} M docs/s, mean batch {rec['mean_batch']:.1f}")
+            results.append(rec)
     gc.enable()
     del tok, codes, pool, pq
     torch.cuda.empty_cache()
-    return {"pool_docs": n_pool, "pool_tokens": T, "k": k, "levels": results}
+    return {"pool_docs": n_pool, "pool_tokens": T, "k": k, "saturation": saturation,
+            "levels": results}
 
 
 def main():
@@ -498,7 +517,11 @@ def main():
                      "launch_config": tuned_entry(args.tune_cache, 2, wl.dim, 2),
                      "alg_bytes_per_launch": alg,
                      "launch_ms_mean": float(fused_ms.mean()),
-                     "launch_ms_median": float(np.median(fused_ms))},
+                     "launch_ms_median": float(np.median(fused_ms)),
+                     "mfma_algorithmic_tflops": R.flops(1, wl.nq, wl.T, wl.dim)
+                     / (fused_ms.mean() * 1e-3) / 1e12,
+                     "mfma_frac_of_f16_peak": R.flops(1, wl.nq, wl.T, wl.dim)
+                     / (fused_ms.mean() * 1e-3) / R.PEAK_FLOPS["f16"]},
     }
     log(f"[bench] fused f16: {fused_ms.mean():.3f} ms/launch, {achieved / 1e12:.2f} TB/s, "
         f"step {ms_per_step:.3f} ms")
