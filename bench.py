@@ -45,6 +45,24 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def host_info():
+    """Machine and software the numbers were taken on."""
+    import torch
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    props = torch.cuda.get_device_properties(0)
+    return {"cpu_model": model, "cpu_threads": os.cpu_count(), "torch": torch.__version__,
+            "hip": torch.version.hip, "gpu": props.name,
+            "gpu_arch": getattr(props, "gcnArchName", ""), "gpu_cus": props.multi_processor_count,
+            "gpu_mem_gb": round(props.total_memory / 1e9, 1)}
+
+
 def tuned_entry(path, dtype, dim, nqb):
     """The tuned launch configuration the library loaded for a key (None:
     the library's built-in default)."""
@@ -524,6 +542,7 @@ def main():
                      "mfma_frac_of_f16_peak": 2.0 * wl.nq * wl.dim * wl.T
                      / (fused_ms.mean() * 1e-3) / R.PEAK_FLOPS["f16"]},
     }
+    out["host"] = host_info()
     log(f"[bench] fused f16: {fused_ms.mean():.3f} ms/launch, {achieved / 1e12:.2f} TB/s, "
         f"step {ms_per_step:.3f} ms")
 

@@ -52,7 +52,8 @@ typedef enum {
   MAXSIM_EINVAL = 1,       /* bad pointer, size, alignment or inconsistent descriptor */
   MAXSIM_EUNSUPPORTED = 2, /* valid request outside what the kernels handle */
   MAXSIM_EWORKSPACE = 3,   /* workspace missing or smaller than *_workspace_size() */
-  MAXSIM_EHIP = 4          /* a HIP runtime call or kernel launch failed */
+  MAXSIM_EHIP = 4,         /* a HIP runtime call or kernel launch failed */
+  MAXSIM_EDEVCHECK = 5     /* maxsim_check found device-side input violations */
 } maxsim_status;
 
 typedef enum {
@@ -230,6 +231,42 @@ maxsim_status maxsim_pq_autotune(const maxsim_csr* queries, const maxsim_pq_docs
                                  const maxsim_candidates* cand, float* scores, void* workspace,
                                  size_t ws_bytes, maxsim_stream_t stream, int32_t reps,
                                  const char* cache_path, char* report, size_t report_len);
+
+/*
+ * Device-side input checks. The scoring calls trust what lives in device
+ * memory (reading it on the host would cost a device-to-host copy per call),
+ * so a caller can check it once, e.g. when a document pool is built or before
+ * a batch is scored. maxsim_validate enqueues, on `stream`, kernels that clear
+ * *flags (a device int32 owned by the caller) and then OR into it one bit per
+ * violated rule:
+ *   MAXSIM_CHECK_DOC_OFFSETS    docs->offsets: offsets[0] == 0, non-decreasing,
+ *                               offsets[n_sets] == n_tokens
+ *   MAXSIM_CHECK_QUERY_OFFSETS  the same for queries
+ *   MAXSIM_CHECK_QUERY_LENGTH   a query longer than queries->max_len
+ *   MAXSIM_CHECK_CAND_OFFSETS   cand->offsets: 0 first, non-decreasing, n_total last
+ *   MAXSIM_CHECK_CAND_IDS       a candidate id outside [0, n_docs)
+ *   MAXSIM_CHECK_FP8_SCALES     an FP8 token scale that is not a normal power of two
+ *   MAXSIM_CHECK_PQ_CODES       a PQ code >= K
+ * queries and cand may be NULL (not checked). Every access stays inside the
+ * declared array sizes whatever the contents. maxsim_validate_pq does the same
+ * for PQ documents (offsets and codes). maxsim_check synchronises `stream`,
+ * reads *flags and returns MAXSIM_EDEVCHECK, with the violated rules named in
+ * maxsim_last_error(), if any bit is set (MAXSIM_OK otherwise).
+ */
+#define MAXSIM_CHECK_DOC_OFFSETS 1
+#define MAXSIM_CHECK_QUERY_OFFSETS 2
+#define MAXSIM_CHECK_QUERY_LENGTH 4
+#define MAXSIM_CHECK_CAND_OFFSETS 8
+#define MAXSIM_CHECK_CAND_IDS 16
+#define MAXSIM_CHECK_FP8_SCALES 32
+#define MAXSIM_CHECK_PQ_CODES 64
+maxsim_status maxsim_validate(const maxsim_csr* queries, const maxsim_csr* docs,
+                              const maxsim_candidates* cand, int32_t* flags,
+                              maxsim_stream_t stream);
+maxsim_status maxsim_validate_pq(const maxsim_csr* queries, const maxsim_pq_docs* docs,
+                                 const maxsim_candidates* cand, int32_t* flags,
+                                 maxsim_stream_t stream);
+maxsim_status maxsim_check(const int32_t* flags, maxsim_stream_t stream);
 
 /*
  * Measured HBM read ceiling (for reporting the scorers against what the

@@ -85,12 +85,16 @@ def lib():
     L.maxsim_pq_autotune.argtypes = [_P(CSR), _P(PQ), _P(Cand), _vp, _vp, ctypes.c_size_t, _vp,
                                      ctypes.c_int32, ctypes.c_char_p, ctypes.c_char_p,
                                      ctypes.c_size_t]
+    L.maxsim_validate.argtypes = [_P(CSR), _P(CSR), _P(Cand), _vp, _vp]
+    L.maxsim_validate_pq.argtypes = [_P(CSR), _P(PQ), _P(Cand), _vp, _vp]
+    L.maxsim_check.argtypes = [_vp, _vp]
     L.maxsim_load_tune_cache.argtypes = [ctypes.c_char_p]
     L.maxsim_stream_probe.argtypes = [_vp, ctypes.c_size_t, ctypes.c_int32, _vp, ctypes.c_int64,
                                       _vp]
     for name in ("maxsim_quantize", "maxsim_score", "maxsim_score_unfused", "maxsim_pq_score",
                  "maxsim_topk", "maxsim_autotune", "maxsim_pq_autotune",
-                 "maxsim_load_tune_cache", "maxsim_stream_probe"):
+                 "maxsim_load_tune_cache", "maxsim_stream_probe", "maxsim_validate",
+                 "maxsim_validate_pq", "maxsim_check"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     # launch shapes tuned on an MI355X for the shipped key set (missing: defaults)
@@ -290,6 +294,24 @@ def pq_autotune(q: Tokens, d: PQDocs, cand: Candidates = None, reps: int = 3,
                                     ws.numel(), _stream(stream), reps,
                                     cache_path.encode() if cache_path else None, buf, len(buf)))
     return json.loads(buf.value.decode())
+
+
+def validate(d, q: Tokens = None, cand: Candidates = None, stream=None):
+    """Device-side checks of offsets, candidate ids, FP8 scales (Tokens docs)
+    or PQ codes (PQDocs docs); raises MaxSimError (status 5) naming the
+    violated rules. Synchronises the stream."""
+    flags = torch.empty(1, dtype=torch.int32, device=d.offsets.device)
+    qc = q.csr() if q is not None else None
+    cc = cand.c() if cand is not None else None
+    qp = ctypes.byref(qc) if qc is not None else None
+    cp = ctypes.byref(cc) if cc is not None else None
+    if isinstance(d, PQDocs):
+        pc = d.pq()
+        _check(lib().maxsim_validate_pq(qp, ctypes.byref(pc), cp, _ptr(flags), _stream(stream)))
+    else:
+        dc = d.csr()
+        _check(lib().maxsim_validate(qp, ctypes.byref(dc), cp, _ptr(flags), _stream(stream)))
+    _check(lib().maxsim_check(_ptr(flags), _stream(stream)))
 
 
 def stream_probe(buf, variant: int = 0, stream=None):

@@ -29,6 +29,7 @@ SOURCES = [("fused_inst.hip", f"fused_dt{t}", [f"-DFUSED_DT={t}"]) for t in rang
     ("topk.hip", "topk", []),
     ("quantize.hip", "quantize", []),
     ("probe.hip", "probe", []),
+    ("validate.hip", "validate", []),
     ("api.cpp", "api", []),
 ]
 

@@ -626,6 +626,101 @@ maxsim_status maxsim_topk(const float* scores, const int64_t* seg_offsets, int64
   return MAXSIM_OK;
 }
 
+// ---------------------------------------------------- device checks --
+
+namespace {
+
+maxsim_status validate_common(const maxsim_csr* queries, const int64_t* doc_off, int64_t n_docs,
+                              int64_t n_doc_tokens, const maxsim_candidates* cand,
+                              int32_t* flags, hipStream_t s) {
+  hipError_t e = launch_clear_flags(flags, s);
+  if (e == hipSuccess)
+    e = launch_check_offsets(doc_off, n_docs, n_doc_tokens, -1, MAXSIM_CHECK_DOC_OFFSETS, 0, flags,
+                             s);
+  if (e == hipSuccess && queries) {
+    e = launch_check_offsets(queries->offsets, queries->n_sets, queries->n_tokens,
+                             queries->max_len, MAXSIM_CHECK_QUERY_OFFSETS,
+                             MAXSIM_CHECK_QUERY_LENGTH, flags, s);
+    if (e == hipSuccess && queries->dtype == MAXSIM_F8E4M3)
+      e = launch_check_scales(queries->scales, queries->n_tokens, MAXSIM_CHECK_FP8_SCALES, flags,
+                              s);
+  }
+  if (e == hipSuccess && cand) {
+    const int64_t nq = queries ? queries->n_sets : 0;
+    if (queries)
+      e = launch_check_offsets(cand->offsets, nq, cand->n_total, -1, MAXSIM_CHECK_CAND_OFFSETS, 0,
+                               flags, s);
+    if (e == hipSuccess)
+      e = launch_check_ids(cand->doc_ids, cand->n_total, n_docs, MAXSIM_CHECK_CAND_IDS, flags, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "validate launch");
+  return MAXSIM_OK;
+}
+
+maxsim_status check_cand_desc(const maxsim_csr* queries, const maxsim_candidates* cand) {
+  if (!cand) return MAXSIM_OK;
+  if (!queries) return fail(MAXSIM_EINVAL, "validate: candidates need the queries descriptor");
+  if (cand->n_total < 0 || !cand->offsets || (cand->n_total > 0 && !cand->doc_ids))
+    return fail(MAXSIM_EINVAL, "validate: bad candidates descriptor");
+  return MAXSIM_OK;
+}
+
+}  // namespace
+
+maxsim_status maxsim_validate(const maxsim_csr* queries, const maxsim_csr* docs,
+                              const maxsim_candidates* cand, int32_t* flags,
+                              maxsim_stream_t stream) {
+  if (!flags) return fail(MAXSIM_EINVAL, "validate: flags is NULL");
+  maxsim_status st = check_csr(docs, "docs", false);
+  if (st) return st;
+  if (queries && (st = check_csr(queries, "queries", true))) return st;
+  if ((st = check_cand_desc(queries, cand))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  st = validate_common(queries, docs->offsets, docs->n_sets, docs->n_tokens, cand, flags, s);
+  if (st) return st;
+  if (docs->dtype == MAXSIM_F8E4M3) {
+    hipError_t e = launch_check_scales(docs->scales, docs->n_tokens, MAXSIM_CHECK_FP8_SCALES,
+                                       flags, s);
+    if (e != hipSuccess) return hip_fail(e, "validate launch");
+  }
+  return MAXSIM_OK;
+}
+
+maxsim_status maxsim_validate_pq(const maxsim_csr* queries, const maxsim_pq_docs* docs,
+                                 const maxsim_candidates* cand, int32_t* flags,
+                                 maxsim_stream_t stream) {
+  if (!flags) return fail(MAXSIM_EINVAL, "validate: flags is NULL");
+  if (!docs || !docs->offsets || docs->n_docs < 0 || docs->n_tokens < 0 ||
+      (docs->n_tokens > 0 && !docs->codes) || docs->M < 1 || docs->K < 1)
+    return fail(MAXSIM_EINVAL, "validate: bad PQ descriptor");
+  maxsim_status st;
+  if (queries && (st = check_csr(queries, "queries", true))) return st;
+  if ((st = check_cand_desc(queries, cand))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  st = validate_common(queries, docs->offsets, docs->n_docs, docs->n_tokens, cand, flags, s);
+  if (st) return st;
+  hipError_t e = launch_check_codes(docs->codes, docs->n_tokens * docs->M, docs->K,
+                                    MAXSIM_CHECK_PQ_CODES, flags, s);
+  if (e != hipSuccess) return hip_fail(e, "validate launch");
+  return MAXSIM_OK;
+}
+
+maxsim_status maxsim_check(const int32_t* flags, maxsim_stream_t stream) {
+  if (!flags) return fail(MAXSIM_EINVAL, "check: flags is NULL");
+  int32_t v = 0;
+  hipError_t e = hipMemcpyAsync(&v, flags, sizeof v, hipMemcpyDeviceToHost, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "check: reading the flags");
+  if (v == 0) return MAXSIM_OK;
+  static const char* names[] = {"document offsets",  "query offsets", "query longer than max_len",
+                                "candidate offsets", "candidate ids", "FP8 scales",
+                                "PQ codes"};
+  std::string msg = "device check failed:";
+  for (int b = 0; b < 7; ++b)
+    if (v & (1 << b)) msg += std::string(" [") + names[b] + "]";
+  return fail(MAXSIM_EDEVCHECK, "%s", msg.c_str());
+}
+
 // ------------------------------------------------------- read ceiling --
 
 maxsim_status maxsim_stream_probe(const void* buf, size_t bytes, int32_t variant, uint32_t* sink,

@@ -93,5 +93,15 @@ hipError_t launch_quantize(const float* src, int64_t n_tokens, int dim, int dt, 
 hipError_t launch_stream_probe(const void* buf, size_t bytes, int variant, uint32_t* sink,
                                int grid, hipStream_t s);
 
+// ---- device-side input checks (flags: caller's device int32) ----
+hipError_t launch_clear_flags(int32_t* flags, hipStream_t s);
+hipError_t launch_check_offsets(const int64_t* off, int64_t n, int64_t n_tokens, int max_len,
+                                int bit_off, int bit_len, int32_t* flags, hipStream_t s);
+hipError_t launch_check_ids(const int32_t* ids, int64_t n, int64_t n_docs, int bit,
+                            int32_t* flags, hipStream_t s);
+hipError_t launch_check_scales(const float* sc, int64_t n, int bit, int32_t* flags, hipStream_t s);
+hipError_t launch_check_codes(const uint8_t* codes, int64_t n, int K, int bit, int32_t* flags,
+                              hipStream_t s);
+
 // ---- device properties ----
 int device_cu_count();

@@ -85,3 +85,18 @@ def test_pq_and_unfused_validation():
 
 def test_missing_tune_cache_is_a_no_op(tmp_path):
     assert M.lib().maxsim_load_tune_cache(str(tmp_path / "none.json").encode()) == 0
+
+
+def test_validate_rejects_bad_host_arguments():
+    L = M.lib()
+    dc = _csr()
+    # NULL flag word
+    assert L.maxsim_validate(None, ctypes.byref(dc), None, None, None) == 1
+    assert L.maxsim_check(None, None) == 1
+    # candidates without the queries they belong to
+    cc = B.Cand(16, 16, 4)
+    assert L.maxsim_validate(None, ctypes.byref(dc), ctypes.byref(cc), ctypes.c_void_p(16),
+                             None) == 1
+    bad = _csr(dim=96)
+    assert L.maxsim_validate(None, ctypes.byref(bad), None, ctypes.c_void_p(16), None) == 2
+    assert L.maxsim_validate_pq(None, None, None, ctypes.c_void_p(16), None) == 1
