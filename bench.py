@@ -248,6 +248,32 @@ def autotune_extra(wl, cache):
         torch.cuda.empty_cache()
 
 
+def bench_multi_query(wl, counts=(1, 2, 4, 8), nq=32, steps=10):
+    """Several queries against every one of the 1M docs in one launch: queries
+    are grouped so one read of a document tile serves up to 8 blocks of 16
+    query tokens."""
+    import torch
+    import paper_2606_26439_amd as M
+    import workloads as W
+    _, D = wl.tokens("f16")
+    out = []
+    for n in counts:
+        q = W.unit_tokens(n * nq, wl.dim, W.rng(5))
+        qt, _ = M.quantize(torch.from_numpy(q).cuda(), "f16")
+        Q = M.Tokens(qt, torch.from_numpy(np.arange(n + 1, dtype=np.int64) * nq).cuda(), "f16",
+                     None, max_len=nq)
+        sc = torch.empty(n * wl.n_docs, dtype=torch.float32, device="cuda")
+        med, mean, std = time_fn(lambda: M.score(Q, D, out=sc), steps, 2)
+        rec = {"queries": n, "nq": nq, "ms_median": med,
+               "query_doc_pairs_per_s": n * wl.n_docs / (med * 1e-3),
+               "doc_bytes_per_s": wl.alg_bytes("f16") / (med * 1e-3)}
+        log(f"[bench] {n} queries x {nq} tokens vs 1M docs: {med:.3f} ms, "
+            f"{rec['query_doc_pairs_per_s'] / 1e9:.2f} G pairs/s")
+        out.append(rec)
+        del sc
+    return out
+
+
 def bench_dim_tiling(batch_sizes=(500_000,), dims=(64, 256, 512, 768), nq=32, nd=128):
     """Fixed Nd = 128, BF16, one 32-token query, d in {64, 256, 512, 768}."""
     import torch
@@ -443,7 +469,7 @@ def main():
     ap.add_argument("--only", choices=["pq", "dims", "serving"], default=None,
                     help="run one secondary section alone and print its JSON")
     ap.add_argument("--skip", default="", help="comma list of sections to skip: "
-                    "forms,unfused,pq,dims,serving")
+                    "forms,multi,unfused,pq,dims,serving")
     ap.add_argument("--cpu-sample", type=int, default=140000,
                     help="docs for the oracle timing (about 10 s of one core)")
     ap.add_argument("--profile", action="store_true",
@@ -606,6 +632,9 @@ def main():
                 del wl.forms[dt]
                 torch.cuda.empty_cache()
         out["forms"] = forms
+
+    if not args.quick and not args.profile and "multi" not in skip:
+        out["multi_query"] = bench_multi_query(wl)
 
     if not args.quick and not args.profile and "unfused" not in skip:
         top_f16 = set(torch.topk(scores, 100).indices.cpu().numpy().tolist())

@@ -162,7 +162,7 @@ struct FusedPlan {
 };
 
 maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_candidates* cand,
-                         float* scores, FusedPlan& pl) {
+                         float* scores, FusedPlan& pl, bool group_queries = true) {
   maxsim_status st = check_csr(q, "queries", true);
   if (st) return st;
   if ((st = check_csr(d, "docs", false))) return st;
@@ -180,11 +180,25 @@ maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_
   }
   if (n_pairs > 0 && !scores) return fail(MAXSIM_EINVAL, "scores is NULL");
   pl.dt = q->dtype;
-  pl.nqb = nqb_for(q->max_len);
   pl.dch = (q->dim % 128 == 0) ? 128 : 64;
   const int nch = q->dim / pl.dch;
   pl.qreg = nch == 1;
+  // Query units: without candidate lists, queries are grouped so one read of
+  // a document tile serves several of them (up to 8 blocks of 16 query tokens
+  // in VGPRs for 1- and 2-byte types, 4 otherwise).
+  const int bpq = nqb_for(q->max_len);
   const int row_bytes = q->dim * esize(q->dtype);
+  int group = 1;
+  if (!cand && group_queries) {
+    // in LDS (d beyond one chunk) the grouped query blocks leave at least
+    // half of it to the staging ring
+    const int cap = (pl.qreg && esize(q->dtype) <= 2) ? 8 : 4;
+    auto fits = [&](int gr) {
+      return pl.qreg || (size_t)gr * bpq * 16 * row_bytes <= device_info().max_lds / 2;
+    };
+    while (group * 2 * bpq <= cap && group * 2 <= q->n_sets && fits(group * 2)) group *= 2;
+  }
+  pl.nqb = group * bpq;
   pl.lds = (size_t)pl.nqb * 16 * row_bytes;
   if (pl.lds > device_info().max_lds)
     return fail(MAXSIM_EUNSUPPORTED, "query block of %zu bytes exceeds LDS", pl.lds);
@@ -205,6 +219,10 @@ maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_
   P.dim = q->dim;
   P.nch = nch;
   P.row_bytes = row_bytes;
+  P.group = group;
+  P.bpq = bpq;
+  P.n_units = (q->n_sets + group - 1) / group;
+  P.n_upairs = cand ? n_pairs : P.n_units * d->n_sets;
   pl.n_pairs = n_pairs;
   return MAXSIM_OK;
 }
@@ -229,11 +247,12 @@ maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s)
   }
   if (lds > di.max_lds) return fail(MAXSIM_EUNSUPPORTED, "staged tiles need %zu bytes of LDS", lds);
   FusedFns fns = fused_kernel_fns(pl.dt, pl.nqb, pl.dch, cfg.pf, cfg.nw, qm, cfg.stage != 0);
+  if (!fns.launch) return fail(MAXSIM_EUNSUPPORTED, "no fused kernel for %d query blocks here", pl.nqb);
   int occ = fns.occupancy(lds);
   if (occ <= 0) return fail(MAXSIM_EHIP, "fused kernel does not fit on a compute unit");
   int per_cu = cfg.wg_per_cu > 0 ? std::min(cfg.wg_per_cu, occ) : occ;
   int64_t grid = (int64_t)per_cu * di.cus;
-  int64_t need = (pl.n_pairs + cfg.nw - 1) / cfg.nw;  // at least one pair per wave
+  int64_t need = (pl.P.n_upairs + cfg.nw - 1) / cfg.nw;  // at least one work pair per wave
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
   hipError_t e = fns.launch(pl.P, (int)grid, lds, s);
@@ -333,7 +352,7 @@ maxsim_status maxsim_score_unfused(const maxsim_csr* queries, const maxsim_csr* 
                                    float* scores, void* workspace, size_t ws_bytes,
                                    maxsim_stream_t stream) {
   FusedPlan pl;
-  maxsim_status st = plan_fused(queries, docs, nullptr, scores, pl);
+  maxsim_status st = plan_fused(queries, docs, nullptr, scores, pl, /*group_queries=*/false);
   if (st) return st;
   size_t need = maxsim_score_unfused_workspace_size(queries, docs);
   if (need > 0 && (!workspace || ws_bytes < need))

@@ -40,14 +40,15 @@ using ::DT_FP8;
 
 constexpr int F_VALID = 1, F_EMPTY = 2, F_TFIRST = 4, F_TLAST = 8, F_DLAST = 16;
 
-// Position (in flattened tokens) where wave w of W starts.
+// Work pair (unit, doc) where wave w of W starts: equal shares of the
+// document tokens (every unit reads all of them), or of the candidate pairs.
 __device__ int64_t wave_range_begin(const FusedParams& P, int64_t w, int64_t W) {
-  if (w >= W) return P.n_pairs;
+  if (w >= W) return P.n_upairs;
   if (P.cand_off != nullptr || P.tokens_per_query <= 0) {
-    return (P.n_pairs / W) * w + ((P.n_pairs % W) * w) / W;
+    return (P.n_upairs / W) * w + ((P.n_upairs % W) * w) / W;
   }
   const int64_t T = P.tokens_per_query;
-  const int64_t total = P.n_q * T;
+  const int64_t total = P.n_units * T;
   // tau = floor(w * total / W) without 128-bit arithmetic
   int64_t tau = (total / W) * w + ((total % W) * w) / W;
   int64_t a = tau / T;
@@ -97,26 +98,35 @@ __device__ __forceinline__ f32x4 mma_step(f32x4 acc, const u32x4 (&a)[NL], const
   return acc;
 }
 
-// Stage query `a` into LDS in the B-operand layout, threads t0, t0 + nthreads,
-// ... of the caller's group doing the copy. Returns Nq (host-trusted capacity
-// is checked by the caller).
+// The query (0 <= qa < n_q) behind block nb of unit u, or -1, and the row of
+// that query the block's lane row r holds.
+__device__ __forceinline__ int64_t unit_query(const FusedParams& P, int64_t u, int nb) {
+  const int gq = nb / P.bpq;
+  const int64_t qa = u * P.group + gq;
+  return (gq < P.group && qa < P.n_q) ? qa : -1;
+}
+
+// Stage the NQB query blocks of unit u into LDS in the B-operand layout,
+// threads t0, t0 + nthreads, ... of the caller's group doing the copy; rows
+// past a query's end are zero.
 template <int NQB>
-__device__ int stage_query(const FusedParams& P, int64_t a, u32x4* q_lds, int t0, int nthreads) {
-  const int64_t q0 = P.q_off[a];
-  const int nq = (int)(P.q_off[a + 1] - q0);
+__device__ void stage_unit(const FusedParams& P, int64_t u, u32x4* q_lds, int t0, int nthreads) {
   const int ncg = P.row_bytes / 64;  // 16-byte column groups per lane-group row
   const int total = NQB * ncg * 64;
-  const char* qbase = P.q_tok + q0 * P.row_bytes;
   for (int idx = t0; idx < total; idx += nthreads) {
     int ln = idx & 63, rest = idx >> 6;
     int cg = rest % ncg, nb = rest / ncg;
-    int row = nb * 16 + (ln & 15);
-    int beta = cg * 4 + (ln >> 4);
+    const int64_t qa = unit_query(P, u, nb);
     u32x4 v = {0, 0, 0, 0};
-    if (row < nq) v = *(const u32x4*)(qbase + (int64_t)row * P.row_bytes + beta * 16);
+    if (qa >= 0) {
+      const int64_t q0 = P.q_off[qa];
+      const int nq = (int)(P.q_off[qa + 1] - q0);
+      const int row = (nb % P.bpq) * 16 + (ln & 15);
+      const int beta = cg * 4 + (ln >> 4);
+      if (row < nq) v = *(const u32x4*)(P.q_tok + (q0 + row) * P.row_bytes + beta * 16);
+    }
     q_lds[idx] = v;
   }
-  return nq;
 }
 
 // LDS bytes of the per-wave staging ring of the STAGE variant.
@@ -177,7 +187,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
   u32x4* qw = q_lds + (QM == Q_WAVE ? (size_t)wave * NQB * ncg * 64 : 0);
 
   while (pb < pe) {
-    int64_t a, qend;
+    int64_t a, qend;  // a: the unit (with candidate lists: the query)
     if (P.cand_off == nullptr) {
       a = pb / P.n_docs;
       qend = (a + 1) * P.n_docs;
@@ -186,58 +196,77 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       qend = P.cand_off[a + 1];
     }
     const int64_t se = qend < pe ? qend : pe;
-    int nq;
     if constexpr (QM == Q_SHARED) {
       __syncthreads();
-      nq = uniform(stage_query<NQB>(P, a, q_lds, threadIdx.x, NW * 64));
+      stage_unit<NQB>(P, a, q_lds, threadIdx.x, NW * 64);
       __syncthreads();
     } else if constexpr (QM == Q_WAVE) {
       // the wave's own LDS ops complete in order; the fence keeps the
       // compiler from moving the operand reads above the staging writes
       __builtin_amdgcn_wave_barrier();
-      nq = uniform(stage_query<NQB>(P, a, qw, lane, 64));
+      stage_unit<NQB>(P, a, qw, lane, 64);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
-      nq = uniform((int)(P.q_off[a + 1] - P.q_off[a]));
     }
+    // per query of the unit (bit gq): exists, has tokens, exceeds the
+    // caller's length bound (then its scores are NaN: never an overrun)
+    const int bpq = P.bpq;
+    uint32_t valid_m = 0, nonempty_m = 0, poison_m = 0;
+#pragma unroll
+    for (int gq = 0; gq < NQB; ++gq) {
+      const int64_t qa = a * P.group + gq;
+      if (gq < P.group && qa < P.n_q) {
+        const int n = (int)(P.q_off[qa + 1] - P.q_off[qa]);
+        valid_m |= 1u << gq;
+        if (n > 0) nonempty_m |= 1u << gq;
+        if (n > bpq * 16) poison_m |= 1u << gq;
+      }
+    }
+    valid_m = __builtin_amdgcn_readfirstlane(valid_m);
+    nonempty_m = __builtin_amdgcn_readfirstlane(nonempty_m);
+    poison_m = __builtin_amdgcn_readfirstlane(poison_m);
 
     int64_t lo = my_lo > pb ? my_lo : pb;
     const int64_t hi = my_hi < se ? my_hi : se;
     const int64_t pair_base = (P.cand_off == nullptr) ? a * P.n_docs : 0;
 
-    if (nq > NQB * 16) {  // caller's max_len was wrong: poison, never overrun
-      for (int64_t p = lo + lane; p < hi; p += 64) P.scores[p] = __builtin_nanf("");
-      pb = se;
-      continue;
-    }
-
     // Query operand registers (one d-chunk, loaded by the wave itself) and
-    // FP8 query scales.
+    // FP8 query scales, block nb from query unit_query(a, nb).
     u32x4 qreg[QREG ? NQB : 1][NL];
-    if constexpr (QREG) {
-      const char* qbase = P.q_tok + P.q_off[a] * P.row_bytes + g * 16;
-#pragma unroll
-      for (int nb = 0; nb < NQB; ++nb) {
-        const int row = nb * 16 + r;
-#pragma unroll
-        for (int c = 0; c < NL; ++c) {
-          u32x4 v = {0u, 0u, 0u, 0u};
-          if (row < nq) v = *(const u32x4*)(qbase + (int64_t)row * P.row_bytes + c * 64);
-          qreg[nb][c] = v;
-        }
-      }
-    }
     int qsc[NQB];
 #pragma unroll
     for (int nb = 0; nb < NQB; ++nb) {
+      const int64_t qa = unit_query(P, a, nb);
+      int64_t q0 = 0;
+      int nq = 0;
+      if (qa >= 0) {
+        q0 = P.q_off[qa];
+        nq = (int)(P.q_off[qa + 1] - q0);
+      }
+      const int row = (nb % bpq) * 16 + r;
+      if constexpr (QREG) {
+        const char* qrow = P.q_tok + (q0 + row) * P.row_bytes + g * 16;
+#pragma unroll
+        for (int c = 0; c < NL; ++c) {
+          u32x4 v = {0u, 0u, 0u, 0u};
+          if (row < nq) v = *(const u32x4*)(qrow + c * 64);
+          qreg[nb][c] = v;
+        }
+      }
       qsc[nb] = 127;
       if constexpr (DT == DT_FP8) {
-        int row = nb * 16 + r;
-        if (row < nq) qsc[nb] = e8m0_of(P.q_scales[P.q_off[a] + row]);
+        if (row < nq) qsc[nb] = e8m0_of(P.q_scales[q0 + row]);
       }
     }
+    // score index of query gq of the unit for work pair pp
+    auto score_at = [&](int64_t pp, int gq) -> int64_t {
+      return P.cand_off != nullptr ? pp : (a * P.group + gq) * P.n_docs + (pp - pair_base);
+    };
+    auto store = [&](int64_t pp, int gq, float v) {
+      if ((poison_m >> gq) & 1u) v = __builtin_nanf("");
+      P.scores[score_at(pp, gq)] = v;
+    };
 
     // ---- prefetch cursor over the (pair, tile, chunk) steps of [lo, hi) ----
     // Document offsets (and candidate ids) are read with scalar loads from
@@ -362,6 +391,8 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       mx[nb] = -__builtin_inff();
     }
 
+    // document end: per query, max over the 16 rows (two shuffles per
+    // block), sum over its blocks and then its 16 columns (four shuffles)
     auto finalize = [&](int64_t pp) {
       float tot = 0.f;
 #pragma unroll
@@ -371,12 +402,17 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
         v = fmaxf(v, xor_shfl(v, 32));
         tot += v;
         mx[nb] = -__builtin_inff();
+        if ((nb + 1) % bpq == 0) {
+          const int gq = nb / bpq;
+          float t = tot;
+          t += xor_shfl(t, 8);
+          t += xor_shfl(t, 4);
+          t += xor_shfl(t, 2);
+          t += xor_shfl(t, 1);
+          if (lane == 0 && ((valid_m >> gq) & 1u)) store(pp, gq, t);
+          tot = 0.f;
+        }
       }
-      tot += xor_shfl(tot, 8);
-      tot += xor_shfl(tot, 4);
-      tot += xor_shfl(tot, 2);
-      tot += xor_shfl(tot, 1);
-      if (lane == 0) P.scores[pp] = tot;
     };
 
     auto consume = [&](const int s) {
@@ -384,7 +420,11 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       const int64_t pp = fp[s];
       if (!(fl & F_VALID)) return;
       if (fl & F_EMPTY) {
-        if (lane == 0) P.scores[pp] = nq == 0 ? 0.f : -__builtin_inff();
+        if (lane == 0) {
+          for (int gq = 0; gq < NQB; ++gq)
+            if ((valid_m >> gq) & 1u)
+              store(pp, gq, ((nonempty_m >> gq) & 1u) ? -__builtin_inff() : 0.f);
+        }
         return;
       }
       u32x4 bb[NL];
@@ -470,7 +510,8 @@ __global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, floa
   const int64_t ntiles = (T + 15) / 16;
   const int ncg = P.row_bytes / 64;
 
-  const int nq = uniform(stage_query<NQB>(P, a, q_lds, threadIdx.x, NW * 64));
+  stage_unit<NQB>(P, a, q_lds, threadIdx.x, NW * 64);  // group 1: unit a = query a
+  const int nq = uniform((int)(P.q_off[a + 1] - P.q_off[a]));
   __syncthreads();
   int qsc[NQB];
 #pragma unroll

@@ -37,6 +37,17 @@ int occupancy_fused_t(size_t lds) {
 
 template <int NQB, int DCH, int PF, int NW, bool STAGE>
 FusedFns pick_q(int qm) {
+  if constexpr (NQB == 8) {
+    // eight query blocks only with the query operand in VGPRs, and only for
+    // 1- and 2-byte elements (the host never asks for anything else)
+    if constexpr (DT == DT_F32) {
+      return {nullptr, nullptr, STAGE};
+    } else {
+      if (qm != fused_detail::Q_REGS) return {nullptr, nullptr, STAGE};
+      return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE>,
+              occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE>, STAGE};
+    }
+  }
   if (qm == fused_detail::Q_REGS)
     return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE>,
             occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE>, STAGE};
@@ -106,6 +117,7 @@ FusedFns CAT(fused_kernel_fns_, FUSED_DT)(int nqb, int dch, int pf, int nw, int 
                                            bool stage) {
   if (nqb == 1) return pick_dch<1>(dch, pf, nw, qm, stage);
   if (nqb == 2) return pick_dch<2>(dch, pf, nw, qm, stage);
+  if (nqb == 8) return pick_dch<8>(dch, pf, nw, qm, stage);
   return pick_dch<4>(dch, pf, nw, qm, stage);
 }
 

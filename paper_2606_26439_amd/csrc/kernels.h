@@ -24,7 +24,15 @@ struct FusedParams {
   int32_t dim;
   int32_t nch;        // dim / DCH
   int32_t row_bytes;  // dim * element size
+  // Query units: without candidate lists a unit is `group` consecutive
+  // queries that share every document tile read (query a of unit u is
+  // u * group + a, its tokens in blocks a * bpq .. a * bpq + bpq - 1 of 16);
+  // with candidate lists a unit is one query (group 1, bpq = query blocks).
+  int32_t group;
+  int32_t bpq;
   int32_t pad;
+  int64_t n_units;   // ceil(n_q / group)
+  int64_t n_upairs;  // work pairs: n_units * n_docs, or the candidate count
 };
 
 typedef hipError_t (*fused_launch_fn)(const FusedParams&, int grid, size_t lds, hipStream_t);

@@ -155,7 +155,7 @@ _DT_CODE = {"f32": 0, "bf16": 1, "f16": 2, "fp8": 3}
 
 def _force_cfg(tmp_path, dtype, dim, stage, pf, nw, wg_per_cu=0):
     entries = [{"dtype": _DT_CODE[dtype], "dim": dim, "nqb": nqb, "pf": pf, "nw": nw,
-                "wg_per_cu": wg_per_cu, "stage": stage} for nqb in (1, 2, 4)]
+                "wg_per_cu": wg_per_cu, "stage": stage} for nqb in (1, 2, 4, 8)]
     path = tmp_path / f"cfg_{dtype}_{dim}_{stage}_{pf}_{nw}.json"
     path.write_text(json.dumps({"version": 1, "entries": entries}))
     M.load_tune_cache(str(path))
@@ -225,6 +225,37 @@ def test_query_capacity_is_enforced():
     Q = device_tokens(q, q_off, "f16", max_len=32)
     got = M.score(Q, device_tokens(d, d_off, "f16")).cpu().numpy()
     assert np.all(np.isnan(got))
+
+
+@pytest.mark.parametrize("dtype,dim", [("f16", 128), ("fp8", 128), ("bf16", 256), ("f32", 128)])
+def test_grouped_queries_share_document_reads(dtype, dim):
+    # 13 queries of at most 16 tokens (one empty) against all documents: the
+    # kernel scores up to 8 of them per document read (units of 8 + 5)
+    nq_lens = [16, 1, 0, 9, 16, 3, 12, 16, 5, 16, 2, 7, 16]
+    q, q_off, d, d_off = _ragged(140, dim, seed=dim + 71, nq_lens=nq_lens, empty_every=23)
+    Q = device_tokens(q, q_off, dtype, max_len=16)
+    D = device_tokens(d, d_off, dtype)
+    got = M.score(Q, D).cpu().numpy()
+    want = o1_scores(q, q_off, d, d_off, dtype)
+    assert_close_o1(got, want, f"grouped {dtype} d={dim}", dtype)
+    # each query alone gives the same bits as inside its unit
+    for a in (0, 3, 12):
+        Qa = device_tokens(q[q_off[a]:q_off[a + 1]], [0, nq_lens[a]], dtype, max_len=16)
+        alone = M.score(Qa, D).cpu().numpy()
+        assert np.array_equal(alone.view(np.uint32), got[a * 140:(a + 1) * 140].view(np.uint32)), a
+
+
+def test_understated_length_poisons_only_that_query():
+    # max_len 16 but query 1 has 20 tokens: its scores are NaN, the others in
+    # its unit are exact
+    nq_lens = [16, 20, 5, 16]
+    q, q_off, d, d_off = _ragged(60, 128, seed=77, nq_lens=nq_lens)
+    Q = device_tokens(q, q_off, "f16", max_len=16)
+    got = M.score(Q, device_tokens(d, d_off, "f16")).cpu().numpy().reshape(4, 60)
+    assert np.all(np.isnan(got[1]))
+    want = o1_scores(q, q_off, d, d_off, "f16").reshape(4, 60)
+    for a in (0, 2, 3):
+        assert_close_o1(got[a], want[a], f"query {a}", "f16")
 
 
 # ----------------------------------------------------------------- top-k
