@@ -274,6 +274,67 @@ def bench_multi_query(wl, counts=(1, 2, 4, 8), nq=32, steps=10):
     return out
 
 
+def bench_full_corpus(n_docs=8_841_823, nq=32, k=1000, steps=5):
+    """Exhaustive retrieval at MS MARCO passage-collection scale (8.8M
+    synthetic FP16 docs, lognormal lengths, ~156 GB): one 32-token query
+    scored against every document, then the top-k; and 8 queries of 16 tokens
+    in one launch (one document read per tile for all of them)."""
+    import torch
+    import oracle
+    import paper_2606_26439_amd as M
+    import workloads as W
+    from paper_2606_26439_amd import roofline as R
+    lens = W.doc_lengths(n_docs, 0)
+    d_off_np = W.offsets_from_lengths(lens)
+    T = int(d_off_np[-1])
+    samp = np.sort(np.random.default_rng(19).choice(n_docs, size=200, replace=False))
+    rows = np.concatenate([np.arange(d_off_np[b], d_off_np[b + 1]) for b in samp])
+    t0 = time.time()
+    tok, _, f32 = gen_docs(T, 128, "f16", seed=7000, sample_rows=rows)
+    log(f"[bench] full corpus: {n_docs} docs, {T} tokens, {tok.numel() * 2 / 1e9:.1f} GB FP16, "
+        f"built in {time.time() - t0:.1f}s")
+    D = M.Tokens(tok, torch.from_numpy(d_off_np).cuda(), "f16", None, max_len=int(lens.max()))
+    rec = {"n_docs": n_docs, "n_doc_tokens": T, "doc_gb": tok.numel() * 2 / 1e9, "k": k}
+    q = W.unit_tokens(nq, 128, W.rng(1))
+    qt, _ = M.quantize(torch.from_numpy(q).cuda(), "f16")
+    Q = M.Tokens(qt, torch.tensor([0, nq], device="cuda"), "f16", None, max_len=nq)
+    sc = torch.empty(n_docs, dtype=torch.float32, device="cuda")
+    seg = torch.tensor([0, n_docs], dtype=torch.int64, device="cuda")
+    ws = torch.empty(M.topk_workspace_bytes(1, k), dtype=torch.uint8, device="cuda")
+
+    def step():
+        M.score(Q, D, out=sc)
+        M.topk(sc, seg, k, workspace=ws)
+
+    med, mean, std = time_fn(step, steps, 1)
+    med_s, _, _ = time_fn(lambda: M.score(Q, D, out=sc), steps, 1)
+    b = R.fused_bytes(T, n_docs, n_docs, nq, 128, "f16")
+    got = sc[torch.from_numpy(samp).cuda()].cpu().numpy().astype(np.float64)
+    qv, _ = oracle.exact_values(q, "f16")
+    dv, _ = oracle.exact_values(f32, "f16")
+    s_off = W.offsets_from_lengths(lens[samp])
+    want = oracle.maxsim(qv, [0, nq], dv, s_off)
+    rel = float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1.0)))
+    rec.update({"ms_per_query_score_plus_topk": med, "ms_score": med_s,
+                "docs_per_s": n_docs / (med * 1e-3), "hbm_frac": b / (med_s * 1e-3) / HBM_PEAK,
+                "sampled_max_rel_err_vs_o1": rel})
+    log(f"[bench] full corpus, 1 query: score {med_s:.2f} ms ({rec['hbm_frac'] * 100:.1f}% HBM), "
+        f"+ top-{k} {med:.2f} ms, err {rel:.1e}")
+    del sc
+    n8 = 8
+    q8 = W.unit_tokens(n8 * 16, 128, W.rng(2))
+    q8t, _ = M.quantize(torch.from_numpy(q8).cuda(), "f16")
+    Q8 = M.Tokens(q8t, torch.from_numpy(np.arange(n8 + 1, dtype=np.int64) * 16).cuda(), "f16",
+                  None, max_len=16)
+    sc8 = torch.empty(n8 * n_docs, dtype=torch.float32, device="cuda")
+    med8, _, _ = time_fn(lambda: M.score(Q8, D, out=sc8), steps, 1)
+    rec.update({"batch8x16_ms": med8, "batch8x16_query_doc_pairs_per_s": n8 * n_docs / (med8 * 1e-3)})
+    log(f"[bench] full corpus, 8 queries x 16 tokens in one launch: {med8:.2f} ms")
+    del sc8, tok, D
+    torch.cuda.empty_cache()
+    return rec
+
+
 def bench_dim_tiling(batch_sizes=(500_000,), dims=(64, 256, 512, 768), nq=32, nd=128):
     """Fixed Nd = 128, BF16, one 32-token query, d in {64, 256, 512, 768}."""
     import torch
@@ -463,13 +524,13 @@ def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_0
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="headline step only")
-    ap.add_argument("--only", choices=["pq", "dims", "serving"], default=None,
+    ap.add_argument("--only", choices=["pq", "dims", "serving", "corpus"], default=None,
                     help="run one secondary section alone and print its JSON")
     ap.add_argument("--skip", default="", help="comma list of sections to skip: "
-                    "forms,multi,unfused,pq,dims,serving")
+                    "forms,multi,unfused,pq,dims,serving,corpus")
     ap.add_argument("--cpu-sample", type=int, default=140000,
                     help="docs for the oracle timing (about 10 s of one core)")
     ap.add_argument("--profile", action="store_true",
@@ -495,7 +556,8 @@ def main():
         M.load_tune_cache(args.tune_cache)
 
     if args.only:
-        fn = {"pq": bench_pq, "dims": bench_dim_tiling, "serving": bench_serving}[args.only]
+        fn = {"pq": bench_pq, "dims": bench_dim_tiling, "serving": bench_serving,
+              "corpus": bench_full_corpus}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
 
@@ -661,6 +723,8 @@ def main():
             out["dim_tiling"] = bench_dim_tiling()
         if "serving" not in skip:
             out["serving"] = bench_serving()
+        if "corpus" not in skip:
+            out["full_corpus"] = bench_full_corpus()
 
     print(json.dumps(out), flush=True)
 
