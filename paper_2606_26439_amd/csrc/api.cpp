@@ -180,7 +180,11 @@ maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_
   }
   if (n_pairs > 0 && !scores) return fail(MAXSIM_EINVAL, "scores is NULL");
   pl.dt = q->dtype;
+  // d-chunk width: 128 (the paper's dimension tiling), 64 when d is not a
+  // multiple of 128, and 256 for 1- and 2-byte rows of d >= 512 (same k
+  // order, so the same bits; each row read becomes 512 contiguous bytes)
   pl.dch = (q->dim % 128 == 0) ? 128 : 64;
+  if (esize(q->dtype) <= 2 && q->dim >= 512 && q->dim % 256 == 0) pl.dch = 256;
   const int nch = q->dim / pl.dch;
   pl.qreg = nch == 1;
   // Query units: without candidate lists, queries are grouped so one read of
@@ -230,9 +234,18 @@ maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_
 maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s) {
   if (pl.n_pairs == 0) return MAXSIM_OK;
   DevInfo di = device_info();
+  // 256-wide chunks exist only with LDS-staged tiles, and only where their
+  // ring fits beside one copy of the query blocks; else 128-wide
+  FusedParams P = pl.P;
+  int dch = pl.dch;
+  if (dch == 256 && (!cfg.stage || pl.lds + (size_t)cfg.nw * cfg.pf * 16 * 256 * esize(pl.dt) >
+                                       di.max_lds)) {
+    dch = 128;
+    P.nch = P.dim / dch;
+  }
   // query operand: VGPRs when d fits one chunk, else one LDS copy per wave
   // when that fits beside the staging ring, else one per workgroup
-  const size_t ring = cfg.stage ? (size_t)cfg.nw * cfg.pf * 16 * pl.dch * esize(pl.dt) : 0;
+  const size_t ring = cfg.stage ? (size_t)cfg.nw * cfg.pf * 16 * dch * esize(pl.dt) : 0;
   int qm;
   size_t lds;
   if (pl.qreg) {
@@ -246,7 +259,7 @@ maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s)
     lds = pl.lds + ring;
   }
   if (lds > di.max_lds) return fail(MAXSIM_EUNSUPPORTED, "staged tiles need %zu bytes of LDS", lds);
-  FusedFns fns = fused_kernel_fns(pl.dt, pl.nqb, pl.dch, cfg.pf, cfg.nw, qm, cfg.stage != 0);
+  FusedFns fns = fused_kernel_fns(pl.dt, pl.nqb, dch, cfg.pf, cfg.nw, qm, cfg.stage != 0);
   if (!fns.launch) return fail(MAXSIM_EUNSUPPORTED, "no fused kernel for %d query blocks here", pl.nqb);
   int occ = fns.occupancy(lds);
   if (occ <= 0) return fail(MAXSIM_EHIP, "fused kernel does not fit on a compute unit");
@@ -255,7 +268,7 @@ maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s)
   int64_t need = (pl.P.n_upairs + cfg.nw - 1) / cfg.nw;  // at least one work pair per wave
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
-  hipError_t e = fns.launch(pl.P, (int)grid, lds, s);
+  hipError_t e = fns.launch(P, (int)grid, lds, s);
   if (e != hipSuccess) return hip_fail(e, "fused MaxSim launch");
   return MAXSIM_OK;
 }
@@ -301,8 +314,9 @@ bool json_int(const char* obj, const char* key, int& v) {
 }  // namespace
 
 // =================================================================== ABI ==
-
-extern "C" {
+// Every exported function is declared in maxsim.h inside extern "C", so its
+// definition below has C linkage; the helpers in the anonymous namespaces
+// between them are internal C++.
 
 int maxsim_abi_version(void) { return MAXSIM_ABI_VERSION; }
 
@@ -354,6 +368,10 @@ maxsim_status maxsim_score_unfused(const maxsim_csr* queries, const maxsim_csr* 
   FusedPlan pl;
   maxsim_status st = plan_fused(queries, docs, nullptr, scores, pl, /*group_queries=*/false);
   if (st) return st;
+  if (pl.dch == 256) {  // the comparator's tiles are 128 wide at most
+    pl.dch = 128;
+    pl.P.nch = queries->dim / 128;
+  }
   size_t need = maxsim_score_unfused_workspace_size(queries, docs);
   if (need > 0 && (!workspace || ws_bytes < need))
     return fail(MAXSIM_EWORKSPACE, "unfused: workspace needs %zu bytes", need);
@@ -877,5 +895,3 @@ maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
   }
   return MAXSIM_OK;
 }
-
-}  // extern "C"

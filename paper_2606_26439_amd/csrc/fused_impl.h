@@ -3,30 +3,32 @@
 // Fused kernel: Algorithm 3 ("V2-MQ") of the paper with the query block equal
 // to the whole query (BQ = Nq), so each document byte crosses HBM once
 // (Theorem 1), re-designed for gfx950:
-//   * a document tile is 16 rows x one d-chunk (DCH = 128, or 64 when d is
-//     not a multiple of 128); lane (r, g) = (lane % 16, lane / 16) loads row r,
-//     bytes [c*64 + g*16, +16) of the chunk for c < NL, straight into the MFMA
-//     A-operand registers: every wave instruction covers 16 aligned 64-byte
-//     segments, and a PF-deep ring of such register buffers keeps
-//     PF * 4 KiB (FP16) per wave in flight;
+//   * a document tile is 16 rows x one d-chunk (DCH = 128, the paper's
+//     dimension tiling; 64 when d is not a multiple of 128; 256 for 1- and
+//     2-byte rows of d >= 512, the same k order in longer contiguous reads);
+//     lane (r, g) = (lane % 16, lane / 16) consumes row r, bytes
+//     [c*64 + g*16, +16) of the chunk for c < NL as its MFMA A operand, either
+//     loaded straight into VGPRs or staged through a per-wave LDS ring by
+//     non-temporal global_load_lds (STAGE); PF steps per wave are in flight;
 //   * rows past a document's end are clamped to its last row: a duplicated
 //     token never changes a max (Eq. 1), costs no HBM traffic (the line is
 //     already in cache) and needs no -inf masking;
-//   * Q lives in LDS (shared by the workgroup) in the MFMA B-operand layout
-//     [query block nb][16-byte column group][lane], or in VGPRs when d fits
-//     one chunk; S_t^T = D_t Q^T runs on v_mfma_f32_16x16x{32 f16/bf16,
-//     128 f8f6f4, 4 f32}; the d-chunks of a tile accumulate into the same
-//     FP32 registers before the max (the paper's dimension tiling);
+//   * Q (B operand) lives in VGPRs when d fits one chunk, else in LDS in the
+//     B-operand layout [query block nb][16-byte column group][lane], one copy
+//     per wave or per workgroup; S_t^T = D_t Q^T runs on
+//     v_mfma_f32_16x16x{32 f16/bf16, 128 f8f6f4, 4 f32}; the d-chunks of a
+//     tile accumulate into the same FP32 registers before the max;
 //   * FP8: per-token power-of-two scales go into the E8M0 scale operands of
 //     v_mfma_scale_f32_16x16x128_f8f6f4 (doc row scale on A, query token
 //     scale on B), which is exact for powers of two;
 //   * the running max of query token n (= lane % 16 of block nb) is in-lane
 //     over the 4 accumulator rows; at a document's end two xor-shuffles finish
-//     the max over rows and four more sum the query tokens; one lane stores the
-//     score (no atomics, fixed order: bit-reproducible);
-//   * persistent grid: the (query, doc) pair list is cut into token-balanced
-//     contiguous ranges, one per wave (64-ary wave search over the offsets);
-//     a workgroup reloads Q only where its waves' ranges cross a query.
+//     the max over rows and four more sum a query's tokens; one lane stores
+//     the score (no atomics, fixed order: bit-reproducible);
+//   * without candidate lists, queries are grouped into units whose blocks
+//     share every tile read (one document read for several queries);
+//   * persistent grid: the (unit, doc) work list is cut into token-balanced
+//     contiguous ranges, one per wave (64-ary wave search over the offsets).
 #pragma once
 #include "device_common.h"
 #include "kernels.h"
@@ -209,23 +211,22 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    // per query of the unit (bit gq): exists, has tokens, exceeds the
-    // caller's length bound (then its scores are NaN: never an overrun)
+    // per query gq of the unit, in one word: bit gq = exists, bit 8 + gq =
+    // has tokens, bit 16 + gq = exceeds the caller's length bound (then its
+    // scores are NaN: never an overrun)
     const int bpq = P.bpq;
-    uint32_t valid_m = 0, nonempty_m = 0, poison_m = 0;
+    uint32_t qmask = 0;
 #pragma unroll
     for (int gq = 0; gq < NQB; ++gq) {
       const int64_t qa = a * P.group + gq;
       if (gq < P.group && qa < P.n_q) {
         const int n = (int)(P.q_off[qa + 1] - P.q_off[qa]);
-        valid_m |= 1u << gq;
-        if (n > 0) nonempty_m |= 1u << gq;
-        if (n > bpq * 16) poison_m |= 1u << gq;
+        qmask |= 1u << gq;
+        if (n > 0) qmask |= 1u << (8 + gq);
+        if (n > bpq * 16) qmask |= 1u << (16 + gq);
       }
     }
-    valid_m = __builtin_amdgcn_readfirstlane(valid_m);
-    nonempty_m = __builtin_amdgcn_readfirstlane(nonempty_m);
-    poison_m = __builtin_amdgcn_readfirstlane(poison_m);
+    qmask = __builtin_amdgcn_readfirstlane(qmask);
 
     int64_t lo = my_lo > pb ? my_lo : pb;
     const int64_t hi = my_hi < se ? my_hi : se;
@@ -259,13 +260,12 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
         if (row < nq) qsc[nb] = e8m0_of(P.q_scales[q0 + row]);
       }
     }
-    // score index of query gq of the unit for work pair pp
-    auto score_at = [&](int64_t pp, int gq) -> int64_t {
-      return P.cand_off != nullptr ? pp : (a * P.group + gq) * P.n_docs + (pp - pair_base);
-    };
+    // score index of query gq of the unit for work pair pp: pp + sbase +
+    // gq * n_docs (with candidate lists the unit is one query, sbase 0)
+    const int64_t sbase = (P.cand_off == nullptr) ? a * (P.group - 1) * P.n_docs : 0;
     auto store = [&](int64_t pp, int gq, float v) {
-      if ((poison_m >> gq) & 1u) v = __builtin_nanf("");
-      P.scores[score_at(pp, gq)] = v;
+      if ((qmask >> (16 + gq)) & 1u) v = __builtin_nanf("");
+      P.scores[pp + sbase + (int64_t)gq * P.n_docs] = v;
     };
 
     // ---- prefetch cursor over the (pair, tile, chunk) steps of [lo, hi) ----
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
           t += xor_shfl(t, 4);
           t += xor_shfl(t, 2);
           t += xor_shfl(t, 1);
-          if (lane == 0 && ((valid_m >> gq) & 1u)) store(pp, gq, t);
+          if (lane == 0 && ((qmask >> gq) & 1u)) store(pp, gq, t);
           tot = 0.f;
         }
       }
@@ -422,8 +422,8 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       if (fl & F_EMPTY) {
         if (lane == 0) {
           for (int gq = 0; gq < NQB; ++gq)
-            if ((valid_m >> gq) & 1u)
-              store(pp, gq, ((nonempty_m >> gq) & 1u) ? -__builtin_inff() : 0.f);
+            if ((qmask >> gq) & 1u)
+              store(pp, gq, ((qmask >> (8 + gq)) & 1u) ? -__builtin_inff() : 0.f);
         }
         return;
       }

@@ -37,6 +37,21 @@ int occupancy_fused_t(size_t lds) {
 
 template <int NQB, int DCH, int PF, int NW, bool STAGE>
 FusedFns pick_q(int qm) {
+  if constexpr (DCH == 256) {
+    // wide chunks: LDS-staged, query operand in LDS (d >= 512), at most 4
+    // query blocks, 1- and 2-byte elements
+    if constexpr (DT == DT_F32 || NQB == 8 || !STAGE) {
+      return {nullptr, nullptr, STAGE};
+    } else {
+      if (qm == fused_detail::Q_WAVE)
+        return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_WAVE, STAGE>,
+                occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_WAVE, STAGE>, STAGE};
+      if (qm == fused_detail::Q_SHARED)
+        return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_SHARED, STAGE>,
+                occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_SHARED, STAGE>, STAGE};
+      return {nullptr, nullptr, STAGE};
+    }
+  }
   if constexpr (NQB == 8) {
     // eight query blocks only with the query operand in VGPRs, and only for
     // 1- and 2-byte elements (the host never asks for anything else)
@@ -77,8 +92,9 @@ FusedFns pick_stage(int pf, int nw, int qm, bool stage) {
 
 template <int NQB>
 FusedFns pick_dch(int dch, int pf, int nw, int qm, bool stage) {
-  return dch == 64 ? pick_stage<NQB, 64>(pf, nw, qm, stage)
-                   : pick_stage<NQB, 128>(pf, nw, qm, stage);
+  if (dch == 64) return pick_stage<NQB, 64>(pf, nw, qm, stage);
+  if (dch == 256) return pick_stage<NQB, 256>(pf, nw, qm, stage);
+  return pick_stage<NQB, 128>(pf, nw, qm, stage);
 }
 
 template <int NQB, int DCH>

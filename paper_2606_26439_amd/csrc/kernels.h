@@ -43,7 +43,7 @@ struct FusedFns {
   bool stage;
 };
 
-// dt: maxsim_dtype; nqb: query blocks of 16 (1, 2, 4); dch: 64 or 128;
+// dt: maxsim_dtype; nqb: query blocks of 16 (1, 2, 4, 8); dch: 64, 128 or 256;
 // pf: prefetch depth (2, 3, 4); nw: waves per workgroup (4, 8); qm: where the
 // query operand lives (0: one LDS copy per workgroup, 1: VGPRs, d in one
 // chunk; 2: one LDS copy per wave);

@@ -162,7 +162,7 @@ def _force_cfg(tmp_path, dtype, dim, stage, pf, nw, wg_per_cu=0):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("dim", [64, 128, 256])
+@pytest.mark.parametrize("dim", [64, 128, 256, 768])
 def test_every_launch_configuration_is_bit_identical(tmp_path, dtype, dim):
     # Register-direct and LDS-staged tiles, every prefetch depth and
     # workgroup size: the same wave-level arithmetic, so the same bits.
@@ -171,7 +171,6 @@ def test_every_launch_configuration_is_bit_identical(tmp_path, dtype, dim):
     D = device_tokens(d, d_off, dtype)
     want = o1_scores(q, q_off, d, d_off, dtype)
     esz = {"f32": 4, "bf16": 2, "f16": 2, "fp8": 1}[dtype]
-    dch = 128 if dim % 128 == 0 else 64
     ref = None
     try:
         for stage in (0, 1):
@@ -181,6 +180,10 @@ def test_every_launch_configuration_is_bit_identical(tmp_path, dtype, dim):
                     # query operand: VGPRs (one chunk), per-wave LDS copies
                     # if they fit beside the ring, else one shared copy
                     q1 = 4 * 16 * dim * esz
+                    dch = 128 if dim % 128 == 0 else 64
+                    if (stage and esz <= 2 and dim >= 512 and dim % 256 == 0
+                            and q1 + nw * pf * 16 * 256 * esz <= 160 * 1024):
+                        dch = 256  # wide chunks: staged tiles whose ring fits
                     ring = stage * nw * pf * 16 * dch * esz
                     if dim == dch:
                         lds = ring
