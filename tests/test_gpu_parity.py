@@ -263,7 +263,7 @@ def test_understated_length_poisons_only_that_query():
 
 # ----------------------------------------------------------------- top-k
 
-@pytest.mark.parametrize("k", [1, 7, 100])
+@pytest.mark.parametrize("k", [1, 7, 100, 1024])
 def test_topk_bit_exact(k):
     # the last segment has only 3 distinct scores: its boundary set of equal
     # scores overflows the compaction buffer and takes the exact radix path
@@ -382,6 +382,19 @@ def test_pq_candidates(pq_variant):
     want = oracle.pq_decode_score(q.astype(np.float64), q_off, codes, cb.astype(np.float64), d_off,
                                   cand_off, cand_ids)
     assert_close_o1(got, want, f"pq candidates {pq_variant}")
+
+
+@pytest.mark.parametrize("q_dtype,cb_dtype", [("f32", "f16"), ("f16", "f32"), ("f32", "f32")])
+def test_pq_fp32_queries_and_codebooks(q_dtype, cb_dtype):
+    # FP32 inputs go through the table kernel (the decode kernel takes FP16)
+    q, q_off, cb, codes, d_off = _pq_case(250, 8, 256, 16, seed=43, nq_lens=[32, 11, 64])
+    qx = W.unit_tokens(len(q), 128, W.rng(45)) if q_dtype == "f32" else q
+    cbx = (W.rng(44).standard_normal(cb.shape) * 0.25).astype(np.float32) if cb_dtype == "f32" else cb
+    Q = M.Tokens(dev(qx), dev(q_off), q_dtype)
+    D = M.PQDocs(dev(cbx), dev(codes), dev(d_off))
+    got = M.pq_score(Q, D).cpu().numpy()
+    want = oracle.pq_decode_score(qx.astype(np.float64), q_off, codes, cbx.astype(np.float64), d_off)
+    assert_close_o1(got, want, f"pq q={q_dtype} cb={cb_dtype}")
 
 
 def test_pq_autotune_keeps_results_within_tolerance(tmp_path):
