@@ -248,6 +248,37 @@ def autotune_extra(wl, cache):
         torch.cuda.empty_cache()
 
 
+def bench_plain_fp32():
+    """The small plain case: one 32-token query against 4,096 docs of 32
+    tokens, FP32, seed 0; every score against the oracle, which is timed in
+    full (well below the HBM regime: 67 MB of documents)."""
+    import torch
+    import oracle
+    import paper_2606_26439_amd as M
+    import workloads as W
+    c = W.plain_fp32_case()
+    qt, _ = M.quantize(torch.from_numpy(c["q"]).cuda(), "f32")
+    dt, _ = M.quantize(torch.from_numpy(c["d"]).cuda(), "f32")
+    Q = M.Tokens(qt, torch.from_numpy(c["q_off"]).cuda(), "f32", None, max_len=32)
+    D = M.Tokens(dt, torch.from_numpy(c["d_off"]).cuda(), "f32", None, max_len=32)
+    sc = torch.empty(4096, dtype=torch.float32, device="cuda")
+    med, _, _ = time_fn(lambda: M.score(Q, D, out=sc), 50, 5)
+    t0 = time.perf_counter()
+    want = oracle.maxsim(c["q"].astype(np.float64), c["q_off"], c["d"].astype(np.float64),
+                         c["d_off"])
+    secs = time.perf_counter() - t0
+    got = sc.cpu().numpy().astype(np.float64)
+    rel = float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1.0)))
+    gi = M.topk(sc, torch.tensor([0, 4096], device="cuda"), 100)[1].cpu().numpy()[0]
+    wi, _ = oracle.topk(want, 100)
+    rec = {"n_docs": 4096, "nd": 32, "ms_median": med, "docs_per_s": 4096 / (med * 1e-3),
+           "oracle_s": secs, "oracle_docs_per_s": 4096 / secs, "max_rel_err_vs_oracle": rel,
+           "top100_identical_to_oracle": bool(np.array_equal(gi, wi))}
+    log(f"[bench] plain fp32 4096 docs: {med * 1e3:.1f} us, oracle {secs:.2f} s, err {rel:.1e}, "
+        f"top-100 identical {rec['top100_identical_to_oracle']}")
+    return rec
+
+
 def bench_multi_query(wl, counts=(1, 2, 4, 8), nq=32, steps=10):
     """Several queries against every one of the 1M docs in one launch: queries
     are grouped so one read of a document tile serves up to 8 blocks of 16
@@ -335,7 +366,8 @@ def bench_full_corpus(n_docs=8_841_823, nq=32, k=1000, steps=5):
     return rec
 
 
-def bench_dim_tiling(batch_sizes=(500_000,), dims=(64, 256, 512, 768), nq=32, nd=128):
+def bench_dim_tiling(batch_sizes=(100_000, 250_000, 500_000), dims=(64, 256, 512, 768), nq=32,
+                     nd=128):
     """Fixed Nd = 128, BF16, one 32-token query, d in {64, 256, 512, 768}."""
     import torch
     import oracle
@@ -530,7 +562,7 @@ def main():
     ap.add_argument("--only", choices=["pq", "dims", "serving", "corpus"], default=None,
                     help="run one secondary section alone and print its JSON")
     ap.add_argument("--skip", default="", help="comma list of sections to skip: "
-                    "forms,multi,unfused,pq,dims,serving,corpus")
+                    "plain,forms,multi,unfused,pq,dims,serving,corpus")
     ap.add_argument("--cpu-sample", type=int, default=140000,
                     help="docs for the oracle timing (about 10 s of one core)")
     ap.add_argument("--profile", action="store_true",
@@ -694,6 +726,9 @@ def main():
                 del wl.forms[dt]
                 torch.cuda.empty_cache()
         out["forms"] = forms
+
+    if not args.quick and not args.profile and "plain" not in skip:
+        out["plain_fp32"] = bench_plain_fp32()
 
     if not args.quick and not args.profile and "multi" not in skip:
         out["multi_query"] = bench_multi_query(wl)
