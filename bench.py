@@ -476,22 +476,29 @@ def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_0
     import paper_2606_26439_amd as M
     import workloads as W
     from paper_2606_26439_amd import serve as S
+    import oracle
     t0 = time.time()
     lens = W.doc_lengths(n_pool, 0)
     d_off_np = W.offsets_from_lengths(lens)
     T = int(d_off_np[-1])
-    tok, _, _ = gen_docs(T, 128, "f16", seed=5000)
-    d_off = torch.from_numpy(d_off_np).cuda()
-    pool = M.Tokens(tok, d_off, "f16", None, max_len=int(lens.max()))
-    codes = W.pq_codes_gpu(T, 8, 256, seed=2)
-    pq = M.PQDocs(torch.from_numpy(W.pq_codebooks(8, 256, 16, seed=2)).cuda(), codes, d_off)
-    log(f"[bench] serving pool: {n_pool} docs, {T} tokens, "
-        f"{tok.numel() * 2 / 1e9:.1f} GB FP16 + {codes.numel() / 1e9:.2f} GB codes, "
-        f"built in {time.time() - t0:.1f}s")
     g = W.rng(1)
     nqs = g.integers(8, 65, size=n_sets)
     queries = [W.unit_tokens(int(n), 128, g) for n in nqs]
     c_off, c_ids = W.candidates(n_sets, n_pool, seed=4)
+    # the three smallest candidate sets are checked against the oracle: keep
+    # the FP32 source rows of their documents while the pool is built
+    check_sets = np.argsort(np.diff(c_off), kind="stable")[:3]
+    check_docs = np.unique(np.concatenate([c_ids[c_off[j]:c_off[j + 1]] for j in check_sets]))
+    check_rows = np.concatenate([np.arange(d_off_np[b], d_off_np[b + 1]) for b in check_docs])
+    tok, _, check_f32 = gen_docs(T, 128, "f16", seed=5000, sample_rows=check_rows)
+    d_off = torch.from_numpy(d_off_np).cuda()
+    pool = M.Tokens(tok, d_off, "f16", None, max_len=int(lens.max()))
+    codes = W.pq_codes_gpu(T, 8, 256, seed=2)
+    cb_np = W.pq_codebooks(8, 256, 16, seed=2)
+    pq = M.PQDocs(torch.from_numpy(cb_np).cuda(), codes, d_off)
+    log(f"[bench] serving pool: {n_pool} docs, {T} tokens, "
+        f"{tok.numel() * 2 / 1e9:.1f} GB FP16 + {codes.numel() / 1e9:.2f} GB codes, "
+        f"built in {time.time() - t0:.1f}s")
     counter = [0]
 
     def mk(mode):
@@ -547,10 +554,48 @@ def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_0
                 f"{rec['docs_per_s'] / 1e6:.1f} M docs/s, mean batch {rec['mean_batch']:.1f}")
             results.append(rec)
     gc.enable()
+    # served results of the checked sets (exact and PQ) against the oracle:
+    # scores of the returned ids, and the ids against the oracle's top-k
+    # (a swap is allowed only between near-ties)
+    row_of = {int(r): i for i, r in enumerate(check_rows)}
+    worst, id_ok, n_checked = 0.0, True, 0
+    for mode in ("exact", "pq"):
+        reqs = [S.Request(10 ** 9 + j, queries[j], c_ids[c_off[j]:c_off[j + 1]], mode=mode)
+                for j in check_sets]
+        S.Server(S.Scheduler(128, k), backend).run(reqs)
+        for r, j in zip(reqs, check_sets):
+            qv, _ = oracle.exact_values(r.query, "f16")
+            nq = len(qv)
+            docs = r.cand_ids
+            lens_c = lens[docs]
+            s_off = np.zeros(len(docs) + 1, np.int64)
+            np.cumsum(lens_c, out=s_off[1:])
+            rows = np.concatenate([np.arange(d_off_np[b], d_off_np[b + 1]) for b in docs])
+            if mode == "pq":
+                cc = codes[torch.from_numpy(rows).cuda()].cpu().numpy()
+                want = oracle.pq_decode_score(qv, [0, nq], cc, cb_np.astype(np.float64), s_off)
+            else:
+                dv, _ = oracle.exact_values(check_f32[[row_of[int(x)] for x in rows]], "f16")
+                want = oracle.maxsim(qv, [0, nq], dv, s_off)
+            by_id = dict(zip(docs.tolist(), want.tolist()))
+            kk = min(k, len(docs))
+            got = r.top_ids[:kk].tolist()
+            err = np.abs(r.top_scores[:kk].astype(np.float64) - [by_id[i] for i in got])
+            worst = max(worst, float(np.max(err / np.maximum(np.abs([by_id[i] for i in got]), 1.0))))
+            ex_ids, ex_s = oracle.topk(want, kk, docs.astype(np.int64))
+            for i in set(got) ^ set(ex_ids.tolist()):
+                if abs(by_id[i] - float(ex_s[kk - 1])) > 1e-5 * 64:
+                    id_ok = False
+            n_checked += 1
+    log(f"[bench] serving: {n_checked} served requests vs oracle: max rel err {worst:.1e}, "
+        f"top-{k} ids agree {id_ok}")
     del tok, codes, pool, pq
     torch.cuda.empty_cache()
     return {"pool_docs": n_pool, "pool_tokens": T, "k": k, "saturation": saturation,
-            "levels": results}
+            "levels": results,
+            "sampled_requests_vs_oracle": {"n": n_checked, "max_rel_err": worst,
+                                           "topk_ids_agree_up_to_near_ties": id_ok,
+                                           "candidate_set_sizes": np.diff(c_off)[check_sets].tolist()}}
 
 
 def main():
