@@ -102,6 +102,7 @@ struct FusedCfg {
   int nw = 4;
   int wg_per_cu = 0;  // 0: as many as fit
   int stage = 0;      // 1: document tiles staged through LDS
+  int rows = 16;      // document rows per step (32: FP8, staged, Q in VGPRs)
 };
 
 std::mutex g_tune_mu;
@@ -243,9 +244,11 @@ maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s)
     dch = 128;
     P.nch = P.dim / dch;
   }
+  // 32-row steps only where they exist (FP8, staged, one chunk)
+  const int rt = (cfg.rows == 32 && cfg.stage && pl.qreg && pl.dt == MAXSIM_F8E4M3) ? 32 : 16;
   // query operand: VGPRs when d fits one chunk, else one LDS copy per wave
   // when that fits beside the staging ring, else one per workgroup
-  const size_t ring = cfg.stage ? (size_t)cfg.nw * cfg.pf * 16 * dch * esize(pl.dt) : 0;
+  const size_t ring = cfg.stage ? (size_t)cfg.nw * cfg.pf * rt * dch * esize(pl.dt) : 0;
   int qm;
   size_t lds;
   if (pl.qreg) {
@@ -259,7 +262,7 @@ maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s)
     lds = pl.lds + ring;
   }
   if (lds > di.max_lds) return fail(MAXSIM_EUNSUPPORTED, "staged tiles need %zu bytes of LDS", lds);
-  FusedFns fns = fused_kernel_fns(pl.dt, pl.nqb, dch, cfg.pf, cfg.nw, qm, cfg.stage != 0);
+  FusedFns fns = fused_kernel_fns(pl.dt, pl.nqb, dch, cfg.pf, cfg.nw, qm, cfg.stage != 0, rt);
   if (!fns.launch) return fail(MAXSIM_EUNSUPPORTED, "no fused kernel for %d query blocks here", pl.nqb);
   int occ = fns.occupancy(lds);
   if (occ <= 0) return fail(MAXSIM_EHIP, "fused kernel does not fit on a compute unit");
@@ -282,9 +285,9 @@ std::string cfg_json_all() {
     char b[192];
     snprintf(b, sizeof b,
              "%s{\"dtype\":%d,\"dim\":%d,\"nqb\":%d,\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d,"
-             "\"stage\":%d}",
+             "\"stage\":%d,\"rows\":%d}",
              first ? "" : ",", kv.first.dt, kv.first.dim, kv.first.nqb, kv.second.pf, kv.second.nw,
-             kv.second.wg_per_cu, kv.second.stage);
+             kv.second.wg_per_cu, kv.second.stage, kv.second.rows);
     out += b;
     first = false;
   }
@@ -795,7 +798,9 @@ maxsim_status maxsim_load_tune_cache(const char* path) {
         json_int(obj.c_str(), "nqb", k.nqb) && json_int(obj.c_str(), "pf", c.pf) &&
         json_int(obj.c_str(), "nw", c.nw) && json_int(obj.c_str(), "wg_per_cu", c.wg_per_cu)) {
       if (!json_int(obj.c_str(), "stage", c.stage)) c.stage = 0;  // older caches
-      if ((c.pf >= 2 && c.pf <= 4) && (c.nw == 4 || c.nw == 8) && (c.stage == 0 || c.stage == 1))
+      if (!json_int(obj.c_str(), "rows", c.rows)) c.rows = 16;
+      if ((c.pf >= 2 && c.pf <= 4) && (c.nw == 4 || c.nw == 8) && (c.stage == 0 || c.stage == 1) &&
+          (c.rows == 16 || c.rows == 32))
         g_tuned[k] = c;
     }
     pos = end;
@@ -832,17 +837,21 @@ maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(MAXSIM_EHIP, "autotune: event creation failed");
   std::vector<FusedCfg> space;
-  for (int stage : {0, 1})
-    for (int pf : {2, 3, 4})
-      for (int nw : {4, 8})
-        for (int wpc : {0, 1, 2}) {
-          FusedCfg c;
-          c.pf = pf;
-          c.nw = nw;
-          c.wg_per_cu = wpc;
-          c.stage = stage;
-          space.push_back(c);
-        }
+  const bool rows32 = pl.dt == MAXSIM_F8E4M3 && pl.qreg;
+  for (int rows : {16, 32})
+    for (int stage : {0, 1})
+      for (int pf : {2, 3, 4})
+        for (int nw : {4, 8})
+          for (int wpc : {0, 1, 2}) {
+            if (rows == 32 && (!rows32 || !stage)) continue;
+            FusedCfg c;
+            c.pf = pf;
+            c.nw = nw;
+            c.wg_per_cu = wpc;
+            c.stage = stage;
+            c.rows = rows;
+            space.push_back(c);
+          }
   std::string rep = "{\"dtype\":" + std::to_string(pl.dt) + ",\"dim\":" +
                     std::to_string(queries->dim) + ",\"nqb\":" + std::to_string(pl.nqb) +
                     ",\"trials\":[";
@@ -860,8 +869,9 @@ maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
     (void)hipEventElapsedTime(&ms, e0, e1);
     ms /= reps;
     char b[128];
-    snprintf(b, sizeof b, "%s{\"stage\":%d,\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d,\"ms\":%.5f}",
-             first ? "" : ",", c.stage, c.pf, c.nw, c.wg_per_cu, ms);
+    snprintf(b, sizeof b,
+             "%s{\"stage\":%d,\"rows\":%d,\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d,\"ms\":%.5f}",
+             first ? "" : ",", c.stage, c.rows, c.pf, c.nw, c.wg_per_cu, ms);
     rep += b;
     first = false;
     if (ms < best_ms) {
@@ -873,8 +883,9 @@ maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
   (void)hipEventDestroy(e1);
   char b[128];
   snprintf(b, sizeof b,
-           "],\"best\":{\"stage\":%d,\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d,\"ms\":%.5f}}",
-           best.stage, best.pf, best.nw, best.wg_per_cu, best_ms);
+           "],\"best\":{\"stage\":%d,\"rows\":%d,\"pf\":%d,\"nw\":%d,\"wg_per_cu\":%d,"
+           "\"ms\":%.5f}}",
+           best.stage, best.rows, best.pf, best.nw, best.wg_per_cu, best_ms);
   rep += b;
   std::string all;
   {

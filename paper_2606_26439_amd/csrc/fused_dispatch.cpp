@@ -2,21 +2,21 @@
 // compiled for its element type.
 #include "kernels.h"
 
-FusedFns fused_kernel_fns_0(int, int, int, int, int, bool);
-FusedFns fused_kernel_fns_1(int, int, int, int, int, bool);
-FusedFns fused_kernel_fns_2(int, int, int, int, int, bool);
-FusedFns fused_kernel_fns_3(int, int, int, int, int, bool);
+FusedFns fused_kernel_fns_0(int, int, int, int, int, bool, int);
+FusedFns fused_kernel_fns_1(int, int, int, int, int, bool, int);
+FusedFns fused_kernel_fns_2(int, int, int, int, int, bool, int);
+FusedFns fused_kernel_fns_3(int, int, int, int, int, bool, int);
 hipError_t launch_unfused_0(int, int, const FusedParams&, float*, int, size_t, hipStream_t);
 hipError_t launch_unfused_1(int, int, const FusedParams&, float*, int, size_t, hipStream_t);
 hipError_t launch_unfused_2(int, int, const FusedParams&, float*, int, size_t, hipStream_t);
 hipError_t launch_unfused_3(int, int, const FusedParams&, float*, int, size_t, hipStream_t);
 
-FusedFns fused_kernel_fns(int dt, int nqb, int dch, int pf, int nw, int qm, bool stage) {
+FusedFns fused_kernel_fns(int dt, int nqb, int dch, int pf, int nw, int qm, bool stage, int rt) {
   switch (dt) {
-    case 0: return fused_kernel_fns_0(nqb, dch, pf, nw, qm, stage);
-    case 1: return fused_kernel_fns_1(nqb, dch, pf, nw, qm, stage);
-    case 2: return fused_kernel_fns_2(nqb, dch, pf, nw, qm, stage);
-    default: return fused_kernel_fns_3(nqb, dch, pf, nw, qm, stage);
+    case 0: return fused_kernel_fns_0(nqb, dch, pf, nw, qm, stage, rt);
+    case 1: return fused_kernel_fns_1(nqb, dch, pf, nw, qm, stage, rt);
+    case 2: return fused_kernel_fns_2(nqb, dch, pf, nw, qm, stage, rt);
+    default: return fused_kernel_fns_3(nqb, dch, pf, nw, qm, stage, rt);
   }
 }
 

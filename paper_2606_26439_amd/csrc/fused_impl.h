@@ -150,11 +150,16 @@ constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (0x7 << 4
 // when their ranges cross different queries.
 constexpr int Q_SHARED = 0, Q_REGS = 1, Q_WAVE = 2;
 
-template <int DT, int NQB, int DCH, int PF, int NW, int QM, bool STAGE>
+template <int DT, int NQB, int DCH, int PF, int NW, int QM, bool STAGE, int RT = 16>
 __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
   extern __shared__ u32x4 q_lds[];
   constexpr bool QREG = QM == Q_REGS;
   constexpr bool PERWAVE = QM != Q_SHARED;
+  // RT: document rows per step. 32 (two 16-row MFMA tiles) doubles the bytes
+  // each step moves for narrow rows (FP8 at d = 128: 2 KiB -> 4 KiB); staged
+  // tiles with the query operand in VGPRs only.
+  static_assert(RT == 16 || (RT == 32 && STAGE && QREG), "32-row steps: staged, Q in VGPRs");
+  constexpr int SUB = RT / 16;
   constexpr int ESZ = elem_size<DT>::value;
   constexpr int CB = DCH * ESZ;  // bytes of one row within one chunk
   constexpr int NL = CB / 64;    // 16-byte loads per lane per step
@@ -165,11 +170,12 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
   // streams HBM. Chunk p of tile row rho lands in LDS slot rho*CPR +
   // (p ^ swz(rho)), so the 16 rows an MFMA operand read touches fall in 16
   // different bank groups.
-  constexpr int TILE = 16 * CB;
+  constexpr int TILE = RT * CB;
   constexpr int CPR = CB / 16;                    // 16-byte chunks per tile row
   constexpr int SW = CPR < 16 ? CPR : 16;         // XOR width
   constexpr int SWD = 16 / SW;                    // rows sharing a bank-group offset
-  constexpr int LOADS_PER_FILL = NL + (DT == DT_FP8 ? 1 : 0);
+  constexpr int NLS = NL * SUB;                   // LDS-DMA instructions per step
+  constexpr int LOADS_PER_FILL = (STAGE ? NLS : NL) + (DT == DT_FP8 ? SUB : 0);
 
   const int lane = lane_id();
   const int r = lane & 15, g = lane >> 4;
@@ -311,7 +317,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     };
 
     u32x4 buf[STAGE ? 1 : PF][NL];
-    int bsc[PF];
+    int bsc[PF][SUB];
     int flags[PF];
     int64_t fp[PF];
     constexpr int Q_COPIES = QM == Q_SHARED ? 1 : (QM == Q_WAVE ? NW : 0);
@@ -324,22 +330,19 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     auto fill = [&](const int s) {
       int f = 0;
       const char* base = g_zero_row;
-      const float* sptr = (const float*)g_zero_row;
       const bool live = cp < hi && cnd != 0;
       fp[s] = cp;
       if (cp < hi) {
         if (cnd == 0) {
           f = F_VALID | F_EMPTY;
         } else {
-          int row = ctile * 16 + r;
+          int row = ctile * RT + r;
           row = row < cnd ? row : cnd - 1;
-          const int64_t srow = ct0 + row;
-          base = P.d_tok + srow * P.row_bytes + cchunk * CB + g * 16;
-          if constexpr (DT == DT_FP8) sptr = P.d_scales + srow;
+          base = P.d_tok + (ct0 + row) * P.row_bytes + cchunk * CB + g * 16;
           f = F_VALID | (cchunk == 0 ? F_TFIRST : 0) | (cchunk << 8);
           if (cchunk == nch - 1) {
             f |= F_TLAST;
-            if ((ctile + 1) * 16 >= cnd) f |= F_DLAST;
+            if ((ctile + 1) * RT >= cnd) f |= F_DLAST;
           }
         }
       }
@@ -349,12 +352,12 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
         const char* tb = g_zero_row;
         int lim = 0;
         if (live) {
-          tb = P.d_tok + (ct0 + ctile * 16) * P.row_bytes + cchunk * CB;
-          lim = cnd - 1 - ctile * 16;
+          tb = P.d_tok + (ct0 + ctile * RT) * P.row_bytes + cchunk * CB;
+          lim = cnd - 1 - ctile * RT;
         }
         char* slot = ring + s * TILE;
 #pragma unroll
-        for (int w = 0; w < NL; ++w) {
+        for (int w = 0; w < NLS; ++w) {
           const int ch = 64 * w + lane;  // LDS slot of this lane's 16 bytes
           const int rho = ch / CPR, p = ch % CPR;
           const unsigned off =
@@ -367,10 +370,19 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
 #pragma unroll
         for (int c = 0; c < NL; ++c) buf[s][c] = *(const u32x4*)(base + c * 64);
       }
-      if constexpr (DT == DT_FP8) {
-        bsc[s] = e8m0_of(*sptr);
-      } else {
-        bsc[s] = 127;
+#pragma unroll
+      for (int h = 0; h < SUB; ++h) {
+        if constexpr (DT == DT_FP8) {
+          const float* sptr = (const float*)g_zero_row;
+          if (live) {
+            int row = ctile * RT + h * 16 + r;
+            row = row < cnd ? row : cnd - 1;
+            sptr = P.d_scales + ct0 + row;
+          }
+          bsc[s][h] = e8m0_of(*sptr);
+        } else {
+          bsc[s][h] = 127;
+        }
       }
       flags[s] = f;
       if (cp < hi) {
@@ -378,7 +390,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
           next_pair();
         } else if (++cchunk == nch) {
           cchunk = 0;
-          if (++ctile * 16 >= cnd) next_pair();
+          if (++ctile * RT >= cnd) next_pair();
         }
       }
     };
@@ -416,7 +428,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     };
 
     auto consume = [&](const int s) {
-      const int fl = flags[s], sc = bsc[s];
+      const int fl = flags[s], sc = bsc[s][0];
       const int64_t pp = fp[s];
       if (!(fl & F_VALID)) return;
       if (fl & F_EMPTY) {
@@ -431,22 +443,37 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       if constexpr (STAGE) {
         // every later fill issued LOADS_PER_FILL vector memory operations
         __builtin_amdgcn_s_waitcnt(vmcnt_imm((PF - 1) * LOADS_PER_FILL));
-        const char* slot = ring + s * TILE;
-#pragma unroll
-        for (int c = 0; c < NL; ++c)
-          bb[c] = *(const u32x4*)(slot + (r * CPR + ((c * 4 + g) ^ swz(r))) * 16);
-      } else {
-#pragma unroll
-        for (int c = 0; c < NL; ++c) bb[c] = buf[s][c];
       }
       if constexpr (QREG) {
-        // one chunk per tile: every step starts and ends a tile
+        // one chunk per tile: every step starts and ends its tiles
 #pragma unroll
-        for (int nb = 0; nb < NQB; ++nb) {
-          f32x4 t = mma_step<DT, NL>(f32x4{0.f, 0.f, 0.f, 0.f}, bb, qreg[nb], sc, qsc[nb]);
-          mx[nb] = fmaxf(mx[nb], fmaxf(fmaxf(t.x, t.y), fmaxf(t.z, t.w)));
+        for (int h = 0; h < SUB; ++h) {
+          if constexpr (STAGE) {
+            const char* slot = ring + s * TILE;
+            const int row = h * 16 + r;
+#pragma unroll
+            for (int c = 0; c < NL; ++c)
+              bb[c] = *(const u32x4*)(slot + (row * CPR + ((c * 4 + g) ^ swz(row))) * 16);
+          } else {
+#pragma unroll
+            for (int c = 0; c < NL; ++c) bb[c] = buf[s][c];
+          }
+#pragma unroll
+          for (int nb = 0; nb < NQB; ++nb) {
+            f32x4 t = mma_step<DT, NL>(f32x4{0.f, 0.f, 0.f, 0.f}, bb, qreg[nb], bsc[s][h], qsc[nb]);
+            mx[nb] = fmaxf(mx[nb], fmaxf(fmaxf(t.x, t.y), fmaxf(t.z, t.w)));
+          }
         }
       } else {
+        if constexpr (STAGE) {
+          const char* slot = ring + s * TILE;
+#pragma unroll
+          for (int c = 0; c < NL; ++c)
+            bb[c] = *(const u32x4*)(slot + (r * CPR + ((c * 4 + g) ^ swz(r))) * 16);
+        } else {
+#pragma unroll
+          for (int c = 0; c < NL; ++c) bb[c] = buf[s][c];
+        }
         const int chunk = fl >> 8;
         const bool first = (fl & F_TFIRST) != 0;
 #pragma unroll

@@ -11,9 +11,9 @@ namespace {
 
 constexpr int DT = FUSED_DT;
 
-template <int NQB, int DCH, int PF, int NW, int QM, bool STAGE>
+template <int NQB, int DCH, int PF, int NW, int QM, bool STAGE, int RT = 16>
 hipError_t launch_fused_t(const FusedParams& P, int grid, size_t lds, hipStream_t s) {
-  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QM, STAGE>;
+  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QM, STAGE, RT>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
@@ -23,9 +23,9 @@ hipError_t launch_fused_t(const FusedParams& P, int grid, size_t lds, hipStream_
   return hipGetLastError();
 }
 
-template <int NQB, int DCH, int PF, int NW, int QM, bool STAGE>
+template <int NQB, int DCH, int PF, int NW, int QM, bool STAGE, int RT = 16>
 int occupancy_fused_t(size_t lds) {
-  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QM, STAGE>;
+  auto k = fused_detail::fused_maxsim_kernel<DT, NQB, DCH, PF, NW, QM, STAGE, RT>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
           hipSuccess)
@@ -36,7 +36,16 @@ int occupancy_fused_t(size_t lds) {
 }
 
 template <int NQB, int DCH, int PF, int NW, bool STAGE>
-FusedFns pick_q(int qm) {
+FusedFns pick_q(int qm, int rt) {
+  if (rt == 32) {
+    // 32-row steps: FP8 only (narrow rows), staged, query operand in VGPRs
+    if constexpr (DT == DT_FP8 && STAGE && DCH != 256) {
+      if (qm == fused_detail::Q_REGS)
+        return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE, 32>,
+                occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE, 32>, STAGE};
+    }
+    return {nullptr, nullptr, STAGE};
+  }
   if constexpr (DCH == 256) {
     // wide chunks: LDS-staged, query operand in LDS (d >= 512), at most 4
     // query blocks, 1- and 2-byte elements
@@ -74,27 +83,27 @@ FusedFns pick_q(int qm) {
 }
 
 template <int NQB, int DCH, int PF, bool STAGE>
-FusedFns pick_nw(int nw, int qm) {
-  return nw == 8 ? pick_q<NQB, DCH, PF, 8, STAGE>(qm) : pick_q<NQB, DCH, PF, 4, STAGE>(qm);
+FusedFns pick_nw(int nw, int qm, int rt) {
+  return nw == 8 ? pick_q<NQB, DCH, PF, 8, STAGE>(qm, rt) : pick_q<NQB, DCH, PF, 4, STAGE>(qm, rt);
 }
 
 template <int NQB, int DCH, bool STAGE>
-FusedFns pick_pf(int pf, int nw, int qm) {
-  if (pf == 2) return pick_nw<NQB, DCH, 2, STAGE>(nw, qm);
-  if (pf == 3) return pick_nw<NQB, DCH, 3, STAGE>(nw, qm);
-  return pick_nw<NQB, DCH, 4, STAGE>(nw, qm);
+FusedFns pick_pf(int pf, int nw, int qm, int rt) {
+  if (pf == 2) return pick_nw<NQB, DCH, 2, STAGE>(nw, qm, rt);
+  if (pf == 3) return pick_nw<NQB, DCH, 3, STAGE>(nw, qm, rt);
+  return pick_nw<NQB, DCH, 4, STAGE>(nw, qm, rt);
 }
 
 template <int NQB, int DCH>
-FusedFns pick_stage(int pf, int nw, int qm, bool stage) {
-  return stage ? pick_pf<NQB, DCH, true>(pf, nw, qm) : pick_pf<NQB, DCH, false>(pf, nw, qm);
+FusedFns pick_stage(int pf, int nw, int qm, bool stage, int rt) {
+  return stage ? pick_pf<NQB, DCH, true>(pf, nw, qm, rt) : pick_pf<NQB, DCH, false>(pf, nw, qm, rt);
 }
 
 template <int NQB>
-FusedFns pick_dch(int dch, int pf, int nw, int qm, bool stage) {
-  if (dch == 64) return pick_stage<NQB, 64>(pf, nw, qm, stage);
-  if (dch == 256) return pick_stage<NQB, 256>(pf, nw, qm, stage);
-  return pick_stage<NQB, 128>(pf, nw, qm, stage);
+FusedFns pick_dch(int dch, int pf, int nw, int qm, bool stage, int rt) {
+  if (dch == 64) return pick_stage<NQB, 64>(pf, nw, qm, stage, rt);
+  if (dch == 256) return pick_stage<NQB, 256>(pf, nw, qm, stage, rt);
+  return pick_stage<NQB, 128>(pf, nw, qm, stage, rt);
 }
 
 template <int NQB, int DCH>
@@ -130,11 +139,11 @@ hipError_t unfused_dch(const FusedParams& P, float* S, int grid, size_t lds, int
 #define CAT(a, b) CAT2(a, b)
 
 FusedFns CAT(fused_kernel_fns_, FUSED_DT)(int nqb, int dch, int pf, int nw, int qm,
-                                           bool stage) {
-  if (nqb == 1) return pick_dch<1>(dch, pf, nw, qm, stage);
-  if (nqb == 2) return pick_dch<2>(dch, pf, nw, qm, stage);
-  if (nqb == 8) return pick_dch<8>(dch, pf, nw, qm, stage);
-  return pick_dch<4>(dch, pf, nw, qm, stage);
+                                           bool stage, int rt) {
+  if (nqb == 1) return pick_dch<1>(dch, pf, nw, qm, stage, rt);
+  if (nqb == 2) return pick_dch<2>(dch, pf, nw, qm, stage, rt);
+  if (nqb == 8) return pick_dch<8>(dch, pf, nw, qm, stage, rt);
+  return pick_dch<4>(dch, pf, nw, qm, stage, rt);
 }
 
 hipError_t CAT(launch_unfused_, FUSED_DT)(int nqb, int dch, const FusedParams& P, float* S,

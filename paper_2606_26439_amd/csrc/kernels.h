@@ -49,7 +49,8 @@ struct FusedFns {
 // chunk; 2: one LDS copy per wave);
 // stage: document tiles arrive through a per-wave LDS ring (pf slots of
 // 16 rows x dch elements per wave, after the query block) instead of VGPRs.
-FusedFns fused_kernel_fns(int dt, int nqb, int dch, int pf, int nw, int qm, bool stage);
+// rt: document rows per step (16; 32 for FP8 with staged tiles and Q in VGPRs).
+FusedFns fused_kernel_fns(int dt, int nqb, int dch, int pf, int nw, int qm, bool stage, int rt);
 
 hipError_t launch_unfused(int dt, int nqb, int dch, const FusedParams& P, float* S, int grid,
                           size_t lds, hipStream_t s);

@@ -153,53 +153,58 @@ def test_scores_do_not_depend_on_launch_shape():
 _DT_CODE = {"f32": 0, "bf16": 1, "f16": 2, "fp8": 3}
 
 
-def _force_cfg(tmp_path, dtype, dim, stage, pf, nw, wg_per_cu=0):
+def _force_cfg(tmp_path, dtype, dim, stage, pf, nw, wg_per_cu=0, rows=16):
     entries = [{"dtype": _DT_CODE[dtype], "dim": dim, "nqb": nqb, "pf": pf, "nw": nw,
-                "wg_per_cu": wg_per_cu, "stage": stage} for nqb in (1, 2, 4, 8)]
-    path = tmp_path / f"cfg_{dtype}_{dim}_{stage}_{pf}_{nw}.json"
+                "wg_per_cu": wg_per_cu, "stage": stage, "rows": rows} for nqb in (1, 2, 4, 8)]
+    path = tmp_path / f"cfg_{dtype}_{dim}_{stage}_{pf}_{nw}_{rows}.json"
     path.write_text(json.dumps({"version": 1, "entries": entries}))
     M.load_tune_cache(str(path))
+
+
+def _expected_lds(dtype, dim, stage, pf, nw, rows):
+    """LDS bytes the library asks for under a forced configuration (4 query
+    blocks: the cases below have a 64-token query)."""
+    esz = {"f32": 4, "bf16": 2, "f16": 2, "fp8": 1}[dtype]
+    q1 = 4 * 16 * dim * esz
+    dch = 128 if dim % 128 == 0 else 64
+    if (stage and esz <= 2 and dim >= 512 and dim % 256 == 0
+            and q1 + nw * pf * 16 * 256 * esz <= 160 * 1024):
+        dch = 256  # wide chunks: staged tiles whose ring fits
+    rt = 32 if (rows == 32 and stage and dim == dch and dtype == "fp8") else 16
+    ring = stage * nw * pf * rt * dch * esz
+    if dim == dch:  # query operand in VGPRs
+        return ring
+    if nw * q1 + ring <= 160 * 1024:  # one LDS copy per wave
+        return nw * q1 + ring
+    return q1 + ring  # one copy per workgroup
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("dim", [64, 128, 256, 768])
 def test_every_launch_configuration_is_bit_identical(tmp_path, dtype, dim):
     # Register-direct and LDS-staged tiles, every prefetch depth and
-    # workgroup size: the same wave-level arithmetic, so the same bits.
+    # workgroup size, 16- and (FP8) 32-row steps: the same wave-level
+    # arithmetic, so the same bits.
     q, q_off, d, d_off = _ragged(90, dim, seed=dim + 61, nq_lens=[32, 7, 64, 16], empty_every=29)
     Q = device_tokens(q, q_off, dtype)
     D = device_tokens(d, d_off, dtype)
     want = o1_scores(q, q_off, d, d_off, dtype)
-    esz = {"f32": 4, "bf16": 2, "f16": 2, "fp8": 1}[dtype]
+    configs = [(stage, pf, nw, 16) for stage in (0, 1) for pf in (2, 3, 4) for nw in (4, 8)]
+    if dtype == "fp8":
+        configs += [(1, pf, nw, 32) for pf in (2, 3, 4) for nw in (4, 8)]
     ref = None
     try:
-        for stage in (0, 1):
-            for pf in (2, 3, 4):
-                for nw in (4, 8):
-                    _force_cfg(tmp_path, dtype, dim, stage, pf, nw)
-                    # query operand: VGPRs (one chunk), per-wave LDS copies
-                    # if they fit beside the ring, else one shared copy
-                    q1 = 4 * 16 * dim * esz
-                    dch = 128 if dim % 128 == 0 else 64
-                    if (stage and esz <= 2 and dim >= 512 and dim % 256 == 0
-                            and q1 + nw * pf * 16 * 256 * esz <= 160 * 1024):
-                        dch = 256  # wide chunks: staged tiles whose ring fits
-                    ring = stage * nw * pf * 16 * dch * esz
-                    if dim == dch:
-                        lds = ring
-                    elif nw * q1 + ring <= 160 * 1024:
-                        lds = nw * q1 + ring
-                    else:
-                        lds = q1 + ring
-                    if lds > 160 * 1024:
-                        with pytest.raises(M.MaxSimError):
-                            M.score(Q, D)
-                        continue
-                    got = M.score(Q, D).cpu().numpy()
-                    if ref is None:
-                        ref = got
-                        assert_close_o1(got, want, f"{dtype} d={dim}", dtype)
-                    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (stage, pf, nw)
+        for stage, pf, nw, rows in configs:
+            _force_cfg(tmp_path, dtype, dim, stage, pf, nw, rows=rows)
+            if _expected_lds(dtype, dim, stage, pf, nw, rows) > 160 * 1024:
+                with pytest.raises(M.MaxSimError):
+                    M.score(Q, D)
+                continue
+            got = M.score(Q, D).cpu().numpy()
+            if ref is None:
+                ref = got
+                assert_close_o1(got, want, f"{dtype} d={dim}", dtype)
+            assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (stage, pf, nw, rows)
     finally:
         _force_cfg(tmp_path, dtype, dim, 0, 2 if dtype == "f32" else 4, 4)
         M.load_tune_cache(M.default_tune_cache())
