@@ -14,6 +14,8 @@ follows are stated in the C source:
 * :func:`pq_lut_build`      Phase 1 distance table T[i,m,k] (Sec. 4.3).
 * :func:`pq_lut_score`      Phase 2 lookup-sum-max-sum (Sec. 4.3).
 * :func:`pq_decode_score`   decompress-then-score: decode, then Eq. (1).
+* :func:`residual_decode`   centroid + quantized residual decompression.
+* :func:`residual_decode_score` decode, then Eq. (1).
 * :func:`topk`              (score desc, id asc) selection.
 * :func:`round_f16`, :func:`round_bf16`, :func:`round_e4m3`, :func:`quant_e4m3`
   and the matching ``decode_*``: round-to-nearest-even number formats.
@@ -67,6 +69,9 @@ def _load():
     lib.oracle_pq_lut_score.argtypes = [_d, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                         _u8, _i64, ctypes.c_int64, _i32, ctypes.c_int64, _d]
     lib.oracle_pq_lut_score.restype = ctypes.c_int
+    lib.oracle_residual_decode.argtypes = [_i32, _u8, ctypes.c_int64, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_int32, _d, _d, _d]
+    lib.oracle_residual_decode.restype = ctypes.c_int
     lib.oracle_topk.argtypes = [_d, _i64, ctypes.c_int64, ctypes.c_int64, _i64, _d]
     lib.oracle_topk.restype = ctypes.c_int
     for name, bt in (("f16", _u16), ("bf16", _u16), ("e4m3", _u8)):
@@ -158,6 +163,33 @@ def pq_lut_score(table, codes, d_off, doc_sel=None) -> np.ndarray:
 def pq_decode_score(q_tok, q_off, codes, codebooks, d_off, cand_off=None, cand_ids=None):
     """Decompress-then-score (Sec. 4.1): decode every doc token, then Eq. (1)."""
     dec = pq_decode(codes, codebooks)
+    return maxsim(q_tok, q_off, dec, d_off, cand_off, cand_ids)
+
+
+def residual_decode(ids, residuals, centroids, weights, nbits: int) -> np.ndarray:
+    """ids [T] int32, residuals [T, dim*nbits/8] uint8 (packed codes),
+    centroids [n_c, dim], weights [2**nbits] -> decoded [T, dim] FP64."""
+    lib = _load()
+    ids = _c(ids, np.int32)
+    res = _c(residuals, np.uint8)
+    cen = _c(centroids, np.float64)
+    w = _c(weights, np.float64)
+    n_c, dim = cen.shape
+    assert nbits in (1, 2, 4, 8) and len(w) == 1 << nbits
+    T = len(ids)
+    assert res.shape == (T, dim * nbits // 8)
+    out = np.empty((max(T, 1), dim), np.float64)
+    rc = lib.oracle_residual_decode(_p(ids, _i32), _p(res, _u8), T, dim, nbits, n_c,
+                                    _p(cen, _d), _p(w, _d), _p(out, _d))
+    if rc != 0:
+        raise ValueError("oracle_residual_decode: centroid id out of range")
+    return out[:T]
+
+
+def residual_decode_score(q_tok, q_off, ids, residuals, centroids, weights, nbits, d_off,
+                          cand_off=None, cand_ids=None):
+    """Decompress-then-score: decode every doc token, then Eq. (1)."""
+    dec = residual_decode(ids, residuals, centroids, weights, nbits)
     return maxsim(q_tok, q_off, dec, d_off, cand_off, cand_ids)
 
 

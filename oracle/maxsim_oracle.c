@@ -23,6 +23,10 @@
  *                            T[i,m,k] = q_i[m*dsub:(m+1)*dsub] . C[m,k].
  *   - oracle_pq_lut_score  : Phase 2 of Sec. 4.3: s_ij = sum_m T[i,m,c_jm],
  *                            running max over j, sum over i.
+ *   - oracle_residual_decode: centroid plus per-dimension quantized residual
+ *                            (the compressed form of the PLAID/WARP indexes
+ *                            named in Related Work); scoring then applies
+ *                            Eq. (1) to the decoded vectors.
  *   - oracle_topk          : order by (score descending, id ascending), keep k.
  *   - oracle_round_*       : IEEE-style round-to-nearest-even into binary16,
  *                            bfloat16 and OCP FP8 E4M3FN, written from the
@@ -155,6 +159,38 @@ int oracle_pq_lut_score(const double* table, int64_t nq, int32_t M, int32_t K,
       total += best;
     }
     scores[p] = total;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Residual-compressed documents (the centroid + per-dimension         */
+/* quantized residual representation of the PLAID/WARP indexes the     */
+/* paper integrates with, Related Work and the WARP comparison).       */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Decompress: token t is centroid ids[t] plus a residual whose dimension k is
+ * weights[code(t, k)], where code(t, k) is the nbits-wide field at bit
+ * k * nbits of the token's packed row (row_bytes = dim * nbits / 8 bytes;
+ * fields fill each byte from its least significant bit up):
+ *   out[t, k] = centroids[ids[t], k] + weights[code(t, k)].
+ * Returns 0, or -1 on a centroid id outside [0, n_centroids).
+ */
+int oracle_residual_decode(const int32_t* ids, const uint8_t* residuals, int64_t n_tokens,
+                           int32_t dim, int32_t nbits, int32_t n_centroids,
+                           const double* centroids, const double* weights, double* out) {
+  const int64_t row_bytes = (int64_t)dim * nbits / 8;
+  const uint32_t field_mask = (1u << nbits) - 1u;
+  for (int64_t t = 0; t < n_tokens; ++t) {
+    const int32_t c = ids[t];
+    if (c < 0 || c >= n_centroids) return -1;
+    for (int32_t k = 0; k < dim; ++k) {
+      const int64_t bit = (int64_t)k * nbits;
+      const uint32_t byte = residuals[t * row_bytes + bit / 8];
+      const uint32_t code = (byte >> (bit % 8)) & field_mask;
+      out[t * dim + k] = centroids[(int64_t)c * dim + k] + weights[code];
+    }
   }
   return 0;
 }

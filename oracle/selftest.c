@@ -23,6 +23,9 @@ void oracle_pq_lut_build(const double* q, int64_t nq, int32_t M, int32_t K, int3
 int oracle_pq_lut_score(const double* table, int64_t nq, int32_t M, int32_t K,
                         const uint8_t* codes, const int64_t* d_off, int64_t n_docs,
                         const int32_t* doc_sel, int64_t n_sel, double* scores);
+int oracle_residual_decode(const int32_t* ids, const uint8_t* residuals, int64_t n_tokens,
+                           int32_t dim, int32_t nbits, int32_t n_centroids,
+                           const double* centroids, const double* weights, double* out);
 int oracle_topk(const double* scores, const int64_t* ids, int64_t n, int64_t k, int64_t* out_ids,
                 double* out_scores);
 void oracle_round_f16(const float* x, int64_t n, uint16_t* bits);
@@ -97,6 +100,28 @@ static void test_pq(void) {
   CHECK(oracle_pq_lut_score(table, 2, 2, 3, codes, d_off, 3, sel, 2, s) == -1, "lut bad id");
 }
 
+static void test_residual(void) {
+  /* dim 4, 2 bits: byte 0xE4 holds codes 0, 1, 2, 3 (low bits first) */
+  const double cen[] = {1, 2, 3, 4, 0, 0, 0, 0};
+  const double w[] = {-0.5, -0.25, 0.25, 0.5};
+  const int32_t ids[] = {0, 1};
+  const uint8_t res[] = {0xE4, 0x1B};
+  double out[8];
+  CHECK(oracle_residual_decode(ids, res, 2, 4, 2, 2, cen, w, out) == 0, "residual rc");
+  CHECK(out[0] == 0.5 && out[1] == 1.75 && out[2] == 3.25 && out[3] == 4.5, "residual token 0");
+  CHECK(out[4] == 0.5 && out[5] == 0.25 && out[6] == -0.25 && out[7] == -0.5, "residual token 1");
+  const int32_t bad[] = {2};
+  CHECK(oracle_residual_decode(bad, res, 1, 4, 2, 2, cen, w, out) == -1, "residual bad id");
+  /* dim 2, 4 bits: byte 0x21 holds codes 1, 2 */
+  const double w16[16] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15};
+  const uint8_t r4[] = {0x21};
+  const double c2[] = {0.5, 0.5};
+  const int32_t z[] = {0};
+  CHECK(oracle_residual_decode(z, r4, 1, 2, 4, 1, c2, w16, out) == 0 && out[0] == 1.5 &&
+            out[1] == 2.5,
+        "residual 4-bit fields");
+}
+
 static void test_topk(void) {
   const double s[] = {1.0, 3.0, 3.0, -INFINITY, 2.0};
   const int64_t ids[] = {10, 7, 4, 1, 9};
@@ -144,6 +169,7 @@ static void test_formats(void) {
 int main(void) {
   test_maxsim();
   test_pq();
+  test_residual();
   test_topk();
   test_formats();
   if (failures) {

@@ -13,6 +13,12 @@ evaluation):
   sigma 0.5 (so mu = ln 70 - sigma^2 / 2), clipped to [8, 180];
 * PQ centroids: N(0, 1/16) (std 0.25) stored as FP16; codes uniform on
   [0, K) per (token, subspace);
+* residual-compressed documents: centroids are unit-norm Gaussian vectors
+  stored as FP16 (seed 5); each token's centroid id is uniform on
+  [0, n_centroids) and each dimension's residual code uniform on
+  [0, 2^nbits) (seed 6); the residual value of code c is
+  0.02 * Phi^-1((c + 1/2) / 2^nbits), the centre of the c-th
+  equal-probability bucket of N(0, 0.02^2), stored as FP16;
 * serving: Poisson arrivals (exponential gaps), Nq uniform on {8..64},
   candidate-set size uniform on {1000..100000}, ids drawn without
   replacement from the pool.
@@ -24,6 +30,7 @@ reproducible on the same software stack.
 from __future__ import annotations
 
 import math
+from statistics import NormalDist
 
 import numpy as np
 
@@ -119,6 +126,32 @@ def pq_codes(n_tokens: int, M: int = 8, K: int = 256, seed: int = 2) -> np.ndarr
     return rng(seed + 7).integers(0, K, size=(n_tokens, M), dtype=np.uint8)
 
 
+RESIDUAL_SIGMA = 0.02
+
+
+def residual_centroids(n_centroids: int, dim: int = 128, seed: int = 5) -> np.ndarray:
+    """Centroids [n_centroids, dim]: unit-norm Gaussian rows stored as FP16."""
+    return unit_tokens(n_centroids, dim, rng(seed)).astype(np.float16)
+
+
+def residual_weights(nbits: int) -> np.ndarray:
+    """Residual value of each code: bucket centres of N(0, RESIDUAL_SIGMA^2), FP16."""
+    n = 1 << nbits
+    nd = NormalDist(0.0, RESIDUAL_SIGMA)
+    return np.array([nd.inv_cdf((c + 0.5) / n) for c in range(n)]).astype(np.float16)
+
+
+def residual_ids(n_tokens: int, n_centroids: int, seed: int = 6) -> np.ndarray:
+    """Centroid id per token, uniform on [0, n_centroids), int32."""
+    return rng(seed).integers(0, n_centroids, size=n_tokens, dtype=np.int64).astype(np.int32)
+
+
+def residual_codes(n_tokens: int, dim: int, nbits: int, seed: int = 6) -> np.ndarray:
+    """Packed residual codes [n_tokens, dim*nbits/8] uint8: uniform bytes, so
+    every nbits-wide field is uniform on [0, 2^nbits)."""
+    return rng(seed + 11).integers(0, 256, size=(n_tokens, dim * nbits // 8), dtype=np.uint8)
+
+
 def poisson_arrivals(n: int, qps: float, seed: int = 3) -> np.ndarray:
     """Arrival times (s) of an open-loop Poisson process at rate qps."""
     return np.cumsum(rng(seed).exponential(1.0 / qps, size=n))
@@ -193,5 +226,32 @@ def pq_codes_gpu(n_tokens: int, M: int, K: int, seed: int, device="cuda"):
     for s in range(0, n_tokens, step):
         e = min(n_tokens, s + step)
         out[s:e] = torch.randint(0, K, (e - s, M), generator=g, device=device,
+                                 dtype=torch.int32).to(torch.uint8)
+    return out
+
+
+def residual_ids_gpu(n_tokens: int, n_centroids: int, seed: int, device="cuda"):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    out = torch.empty(n_tokens, dtype=torch.int32, device=device)
+    step = GPU_CHUNK_TOKENS * 4
+    for s in range(0, n_tokens, step):
+        e = min(n_tokens, s + step)
+        out[s:e] = torch.randint(0, n_centroids, (e - s,), generator=g, device=device,
+                                 dtype=torch.int32)
+    return out
+
+
+def residual_codes_gpu(n_tokens: int, dim: int, nbits: int, seed: int, device="cuda"):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed + 11)
+    rb = dim * nbits // 8
+    out = torch.empty((n_tokens, rb), dtype=torch.uint8, device=device)
+    step = GPU_CHUNK_TOKENS
+    for s in range(0, n_tokens, step):
+        e = min(n_tokens, s + step)
+        out[s:e] = torch.randint(0, 256, (e - s, rb), generator=g, device=device,
                                  dtype=torch.int32).to(torch.uint8)
     return out
