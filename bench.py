@@ -426,7 +426,7 @@ def bench_pq(n_docs=2_000_000, n_queries=64, nq=32, M_=8, K=256, dsub=16):
     sc = torch.empty(n_pairs, dtype=torch.float32, device="cuda")
     # both PQ scorers timed on this problem; the faster stays selected
     tune = M.pq_autotune(Q, D, reps=2)
-    log(f"[bench] PQ scorers: {tune['trials']}")
+    log(f"[bench] PQ M={M_} dsub={dsub} scorers: {tune['trials']}")
     med, mean, std = time_fn(lambda: M.pq_score(Q, D, out=sc), 3, 1)
     # sampled check: 3 queries x 300 docs, decode-then-score in FP64
     g = np.random.default_rng(13)
@@ -459,11 +459,77 @@ def bench_pq(n_docs=2_000_000, n_queries=64, nq=32, M_=8, K=256, dsub=16):
     if tune["best"]["variant"] == 1:
         fl = 2.0 * n_queries * nq * M_ * dsub * T
         rec["mfma_f16_frac_unpadded"] = fl / (med * 1e-3) / R.PEAK_FLOPS["f16"]
-    log(f"[bench] PQ: {med:.2f} ms, {rec['pairs_per_s'] / 1e9:.2f} G pairs/s, "
+    log(f"[bench] PQ M={M_} dsub={dsub}: {med:.2f} ms, {rec['pairs_per_s'] / 1e9:.2f} G pairs/s, "
         f"LDS gather frac {rec['lds_gather_frac'] * 100:.1f}%, err {worst:.1e}")
     del codes, sc
     torch.cuda.empty_cache()
     return rec
+
+
+def bench_pq_paper_shape():
+    """The paper's own PQ shape (M = 16 sub-quantizers of 8 dimensions), same
+    2M docs and 64 x 32 query tokens as the main PQ workload."""
+    return bench_pq(M_=16, dsub=8)
+
+
+def bench_residual(n_docs=1_000_000, nq=32, dim=128, n_centroids=1 << 17, nbits_list=(2, 1, 4)):
+    """One 32-token query against 1M residual-compressed docs (centroid id +
+    nbits per dimension; 2^17 centroids, the power of two ColBERT-style
+    indexes pick for ~70M token vectors)."""
+    import torch
+    import oracle
+    import paper_2606_26439_amd as M
+    import workloads as W
+    lens = W.doc_lengths(n_docs, 0)
+    d_off_np = W.offsets_from_lengths(lens)
+    T = int(d_off_np[-1])
+    d_off = torch.from_numpy(d_off_np).cuda()
+    cen_np = W.residual_centroids(n_centroids, dim, seed=5)
+    cen = torch.from_numpy(cen_np).cuda()
+    ids = W.residual_ids_gpu(T, n_centroids, seed=6)
+    q_np = W.unit_tokens(nq, dim, W.rng(1)).astype(np.float16)
+    q_off_np = np.array([0, nq], np.int64)
+    Q = M.Tokens(torch.from_numpy(q_np).cuda(), torch.from_numpy(q_off_np).cuda(), "f16",
+                 max_len=nq)
+    sc = torch.empty(n_docs, dtype=torch.float32, device="cuda")
+    g = np.random.default_rng(17)
+    docs = np.sort(g.choice(n_docs, size=300, replace=False))
+    rows = np.concatenate([np.arange(d_off_np[b], d_off_np[b + 1]) for b in docs])
+    rows_t = torch.from_numpy(rows).cuda()
+    s_off = W.offsets_from_lengths(lens[docs])
+    ids_s = ids[rows_t].cpu().numpy()
+    out = {"n_docs": n_docs, "n_doc_tokens": T, "nq": nq, "dim": dim,
+           "n_centroids": n_centroids, "variants": []}
+    for nbits in nbits_list:
+        res = W.residual_codes_gpu(T, dim, nbits, seed=6)
+        w_np = W.residual_weights(nbits)
+        D = M.ResidualDocs(cen, torch.from_numpy(w_np).cuda(), ids, res, d_off, nbits)
+        ws = torch.empty(M.residual_workspace_bytes(Q, D), dtype=torch.uint8, device="cuda")
+        med, mean, std = time_fn(lambda: M.residual_score(Q, D, out=sc, workspace=ws), 20, 3)
+        want = oracle.residual_decode_score(q_np.astype(np.float64), q_off_np, ids_s,
+                                            res[rows_t].cpu().numpy(), cen_np.astype(np.float64),
+                                            w_np.astype(np.float64), nbits, s_off)
+        got = sc[torch.from_numpy(docs).cuda()].cpu().numpy().astype(np.float64)
+        err = float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1.0)))
+        row_b = dim * nbits // 8
+        hbm = (T * (4 + row_b) + 8 * (n_docs + 1) + 4 * n_docs
+               + n_centroids * dim * 2 + 2 * n_centroids * nq * 4 + nq * dim * 2)
+        gather = T * nq * 4  # table entries gathered per token (L2 / last-level cache)
+        rec = {"nbits": nbits, "ms_median": med, "ms_mean": mean, "ms_std": std,
+               "docs_per_s": n_docs / (med * 1e-3), "bytes_per_token_hbm": 4 + row_b,
+               "alg_hbm_bytes": hbm, "hbm_GBps": hbm / (med * 1e-3) / 1e9,
+               "hbm_frac": hbm / (med * 1e-3) / HBM_PEAK,
+               "table_gather_GBps": gather / (med * 1e-3) / 1e9,
+               "sampled_max_rel_err_vs_decode_then_score": err}
+        out["variants"].append(rec)
+        log(f"[bench] residual {nbits}-bit: {med:.3f} ms, {rec['docs_per_s'] / 1e6:.0f} M docs/s, "
+            f"HBM {rec['hbm_GBps']:.0f} GB/s, table gathers {rec['table_gather_GBps']:.0f} GB/s, "
+            f"err {err:.1e}")
+        del res, D, ws
+        torch.cuda.empty_cache()
+    del ids, cen, sc
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_000, k=100,
@@ -604,10 +670,11 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="headline step only")
-    ap.add_argument("--only", choices=["pq", "dims", "serving", "corpus"], default=None,
+    ap.add_argument("--only", choices=["pq", "pq16", "residual", "dims", "serving", "corpus"],
+                    default=None,
                     help="run one secondary section alone and print its JSON")
     ap.add_argument("--skip", default="", help="comma list of sections to skip: "
-                    "plain,forms,multi,unfused,pq,dims,serving,corpus")
+                    "plain,forms,multi,unfused,pq,pq16,residual,dims,serving,corpus")
     ap.add_argument("--cpu-sample", type=int, default=140000,
                     help="docs for the oracle timing (about 10 s of one core)")
     ap.add_argument("--profile", action="store_true",
@@ -633,7 +700,8 @@ def main():
         M.load_tune_cache(args.tune_cache)
 
     if args.only:
-        fn = {"pq": bench_pq, "dims": bench_dim_tiling, "serving": bench_serving,
+        fn = {"pq": bench_pq, "pq16": bench_pq_paper_shape, "residual": bench_residual,
+              "dims": bench_dim_tiling, "serving": bench_serving,
               "corpus": bench_full_corpus}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
@@ -799,6 +867,10 @@ def main():
         torch.cuda.empty_cache()
         if "pq" not in skip:
             out["pq"] = bench_pq()
+        if "pq16" not in skip:
+            out["pq_paper_shape"] = bench_pq_paper_shape()
+        if "residual" not in skip:
+            out["residual"] = bench_residual()
         if "dims" not in skip:
             out["dim_tiling"] = bench_dim_tiling()
         if "serving" not in skip:

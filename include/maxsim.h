@@ -121,6 +121,36 @@ typedef struct {
   int64_t n_tokens;
 } maxsim_pq_docs;
 
+/*
+ * Residual-compressed documents (the centroid plus quantized-residual form of
+ * the PLAID/WARP indexes named in the paper's Related Work and WARP
+ * comparison): token t is
+ *   x_t[k] = centroids[centroid_ids[t], k] + weights[code(t, k)],
+ * where code(t, k) is the nbits-wide field at bit k * nbits of row t of
+ * `residuals` (row_bytes = dim * nbits / 8; fields fill each byte from its
+ * least significant bit up).
+ *   dim in {64, 128, 256}; nbits in {1, 2, 4}; n_centroids >= 1.
+ *   centroids    [n_centroids, dim] F16, 16-byte aligned.
+ *   weights      [2^nbits] F16: the residual value of each code.
+ *   centroid_ids [n_tokens] int32; ids outside [0, n_centroids) are the
+ *                caller's error (the kernel clamps them, so they only give
+ *                wrong scores; maxsim_validate_residual detects them).
+ *   residuals    [n_tokens, row_bytes] uint8, 16-byte aligned.
+ *   offsets      [n_docs + 1] int64 as for maxsim_csr.
+ */
+typedef struct {
+  int32_t dim;
+  int32_t nbits;
+  int64_t n_centroids;
+  const void* centroids;
+  const void* weights;
+  const int32_t* centroid_ids;
+  const uint8_t* residuals;
+  const int64_t* offsets;
+  int64_t n_docs;
+  int64_t n_tokens;
+} maxsim_residual_docs;
+
 int maxsim_abi_version(void);
 const char* maxsim_last_error(void);
 
@@ -179,6 +209,26 @@ size_t maxsim_pq_score_workspace_size(const maxsim_csr* queries, const maxsim_pq
 maxsim_status maxsim_pq_score(const maxsim_csr* queries, const maxsim_pq_docs* docs,
                               const maxsim_candidates* cand, float* scores, void* workspace,
                               size_t ws_bytes, maxsim_stream_t stream);
+
+/*
+ * MaxSim over residual-compressed documents: Eq. (1) on the decoded tokens,
+ * computed as q_i . x_j = q_i . C[id_j] + q_i . r_j. The first call builds
+ * the table P[c, i] = C[c] . q_i (FP32, every centroid against every query
+ * token of the batch) in `workspace`; the fused scorer then reads each
+ * token's id and packed residual once, gathers P[id_j, i], decodes the
+ * residual in registers and adds q_i . r_j before the max over tokens and the
+ * sum over query tokens. Decoded vectors are never written.
+ *   queries    F16, same dim, max_len <= 64.
+ *   cand       as for maxsim_score.
+ *   workspace  maxsim_residual_score_workspace_size() bytes
+ *              (n_centroids * queries->n_tokens * 4, rounded up to 256).
+ */
+size_t maxsim_residual_score_workspace_size(const maxsim_csr* queries,
+                                            const maxsim_residual_docs* docs,
+                                            const maxsim_candidates* cand);
+maxsim_status maxsim_residual_score(const maxsim_csr* queries, const maxsim_residual_docs* docs,
+                                    const maxsim_candidates* cand, float* scores,
+                                    void* workspace, size_t ws_bytes, maxsim_stream_t stream);
 
 /*
  * Top-k per segment (the torch.topk step of the paper's end-to-end pipeline,
@@ -247,9 +297,12 @@ maxsim_status maxsim_pq_autotune(const maxsim_csr* queries, const maxsim_pq_docs
  *   MAXSIM_CHECK_CAND_IDS       a candidate id outside [0, n_docs)
  *   MAXSIM_CHECK_FP8_SCALES     an FP8 token scale that is not a normal power of two
  *   MAXSIM_CHECK_PQ_CODES       a PQ code >= K
+ *   MAXSIM_CHECK_CENTROID_IDS   a residual document's centroid id outside
+ *                               [0, n_centroids)
  * queries and cand may be NULL (not checked). Every access stays inside the
  * declared array sizes whatever the contents. maxsim_validate_pq does the same
- * for PQ documents (offsets and codes). maxsim_check synchronises `stream`,
+ * for PQ documents (offsets and codes), maxsim_validate_residual for
+ * residual-compressed documents (offsets and centroid ids). maxsim_check synchronises `stream`,
  * reads *flags and returns MAXSIM_EDEVCHECK, with the violated rules named in
  * maxsim_last_error(), if any bit is set (MAXSIM_OK otherwise).
  */
@@ -260,12 +313,17 @@ maxsim_status maxsim_pq_autotune(const maxsim_csr* queries, const maxsim_pq_docs
 #define MAXSIM_CHECK_CAND_IDS 16
 #define MAXSIM_CHECK_FP8_SCALES 32
 #define MAXSIM_CHECK_PQ_CODES 64
+#define MAXSIM_CHECK_CENTROID_IDS 128
 maxsim_status maxsim_validate(const maxsim_csr* queries, const maxsim_csr* docs,
                               const maxsim_candidates* cand, int32_t* flags,
                               maxsim_stream_t stream);
 maxsim_status maxsim_validate_pq(const maxsim_csr* queries, const maxsim_pq_docs* docs,
                                  const maxsim_candidates* cand, int32_t* flags,
                                  maxsim_stream_t stream);
+maxsim_status maxsim_validate_residual(const maxsim_csr* queries,
+                                       const maxsim_residual_docs* docs,
+                                       const maxsim_candidates* cand, int32_t* flags,
+                                       maxsim_stream_t stream);
 maxsim_status maxsim_check(const int32_t* flags, maxsim_stream_t stream);
 
 /*

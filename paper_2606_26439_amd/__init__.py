@@ -6,7 +6,8 @@ loop built on it. PyTorch provides device memory and streams only.
 
     from paper_2606_26439_amd import Tokens, quantize, score, topk
 """
-from ._binding import (DTYPES, ELEM_BYTES, Candidates, MaxSimError, PQDocs, Tokens,  # noqa: F401
-                       autotune, default_tune_cache, lib, load_tune_cache, pq_autotune,
-                       pq_score, quantize, score, score_unfused, stream_probe, topk,
+from ._binding import (DTYPES, ELEM_BYTES, Candidates, MaxSimError, PQDocs,  # noqa: F401
+                       ResidualDocs, Tokens, autotune, default_tune_cache, lib,
+                       load_tune_cache, pq_autotune, pq_score, quantize, residual_score,
+                       residual_workspace_bytes, score, score_unfused, stream_probe, topk,
                        topk_workspace_bytes, unfused_workspace_bytes, validate)

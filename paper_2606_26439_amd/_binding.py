@@ -47,6 +47,14 @@ class PQ(ctypes.Structure):
                 ("n_docs", ctypes.c_int64), ("n_tokens", ctypes.c_int64)]
 
 
+class Residual(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nbits", ctypes.c_int32),
+                ("n_centroids", ctypes.c_int64), ("centroids", ctypes.c_void_p),
+                ("weights", ctypes.c_void_p), ("centroid_ids", ctypes.c_void_p),
+                ("residuals", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("n_docs", ctypes.c_int64), ("n_tokens", ctypes.c_int64)]
+
+
 _lib = None
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
@@ -75,6 +83,10 @@ def lib():
     L.maxsim_pq_score_workspace_size.argtypes = [_P(CSR), _P(PQ), _P(Cand)]
     L.maxsim_pq_score_workspace_size.restype = ctypes.c_size_t
     L.maxsim_pq_score.argtypes = [_P(CSR), _P(PQ), _P(Cand), _vp, _vp, ctypes.c_size_t, _vp]
+    L.maxsim_residual_score_workspace_size.argtypes = [_P(CSR), _P(Residual), _P(Cand)]
+    L.maxsim_residual_score_workspace_size.restype = ctypes.c_size_t
+    L.maxsim_residual_score.argtypes = [_P(CSR), _P(Residual), _P(Cand), _vp, _vp,
+                                        ctypes.c_size_t, _vp]
     L.maxsim_topk_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32]
     L.maxsim_topk_workspace_size.restype = ctypes.c_size_t
     L.maxsim_topk.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int64, _vp, ctypes.c_int32, _vp,
@@ -87,6 +99,7 @@ def lib():
                                      ctypes.c_size_t]
     L.maxsim_validate.argtypes = [_P(CSR), _P(CSR), _P(Cand), _vp, _vp]
     L.maxsim_validate_pq.argtypes = [_P(CSR), _P(PQ), _P(Cand), _vp, _vp]
+    L.maxsim_validate_residual.argtypes = [_P(CSR), _P(Residual), _P(Cand), _vp, _vp]
     L.maxsim_check.argtypes = [_vp, _vp]
     L.maxsim_load_tune_cache.argtypes = [ctypes.c_char_p]
     L.maxsim_stream_probe.argtypes = [_vp, ctypes.c_size_t, ctypes.c_int32, _vp, ctypes.c_int64,
@@ -94,7 +107,8 @@ def lib():
     for name in ("maxsim_quantize", "maxsim_score", "maxsim_score_unfused", "maxsim_pq_score",
                  "maxsim_topk", "maxsim_autotune", "maxsim_pq_autotune",
                  "maxsim_load_tune_cache", "maxsim_stream_probe", "maxsim_validate",
-                 "maxsim_validate_pq", "maxsim_check"):
+                 "maxsim_validate_pq", "maxsim_check", "maxsim_residual_score",
+                 "maxsim_validate_residual"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     # launch shapes tuned on an MI355X for the shipped key set (missing: defaults)
@@ -178,6 +192,27 @@ class PQDocs:
                   self.n_docs, self.n_tokens)
 
 
+class ResidualDocs:
+    """Residual-compressed documents: centroids [n_c, dim] f16, weights
+    [2**nbits] f16, centroid_ids [T] int32, residuals [T, dim*nbits/8] uint8
+    (packed codes, low bits first), offsets [n_docs + 1] int64."""
+
+    def __init__(self, centroids, weights, centroid_ids, residuals, offsets, nbits: int):
+        self.centroids, self.weights = centroids, weights
+        self.centroid_ids, self.residuals, self.offsets = centroid_ids, residuals, offsets
+        self.nbits = int(nbits)
+        self.n_centroids, self.dim = (int(x) for x in centroids.shape)
+        self.n_docs = int(offsets.numel()) - 1
+        self.n_tokens = int(centroid_ids.numel())
+
+    def res(self) -> Residual:
+        return Residual(self.dim, self.nbits, self.n_centroids, self.centroids.data_ptr(),
+                        self.weights.data_ptr(),
+                        self.centroid_ids.data_ptr() if self.n_tokens else None,
+                        self.residuals.data_ptr() if self.n_tokens else None,
+                        self.offsets.data_ptr(), self.n_docs, self.n_tokens)
+
+
 def _n_pairs(q: Tokens, n_docs: int, cand):
     return cand.n_total if cand is not None else q.n_sets * n_docs
 
@@ -242,6 +277,32 @@ def pq_score(q: Tokens, d: PQDocs, cand: Candidates = None, out=None, workspace=
     return out
 
 
+def residual_workspace_bytes(q: Tokens, d: ResidualDocs, cand: Candidates = None) -> int:
+    qc, rc = q.csr(), d.res()
+    cc = cand.c() if cand is not None else None
+    return int(lib().maxsim_residual_score_workspace_size(
+        ctypes.byref(qc), ctypes.byref(rc), ctypes.byref(cc) if cc is not None else None))
+
+
+def residual_score(q: Tokens, d: ResidualDocs, cand: Candidates = None, out=None,
+                   workspace=None, stream=None):
+    """MaxSim over residual-compressed documents, same layout as score()."""
+    n = _n_pairs(q, d.n_docs, cand)
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.float32, device=d.offsets.device)
+    qc, rc = q.csr(), d.res()
+    cc = cand.c() if cand is not None else None
+    ccp = ctypes.byref(cc) if cc is not None else None
+    need = int(lib().maxsim_residual_score_workspace_size(ctypes.byref(qc), ctypes.byref(rc), ccp))
+    if workspace is None and need > 0:
+        workspace = torch.empty(need, dtype=torch.uint8, device=d.offsets.device)
+    _check(lib().maxsim_residual_score(ctypes.byref(qc), ctypes.byref(rc), ccp, _ptr(out),
+                                       _ptr(workspace),
+                                       0 if workspace is None else workspace.numel(),
+                                       _stream(stream)))
+    return out
+
+
 def topk_workspace_bytes(n_segments: int, k: int) -> int:
     return int(lib().maxsim_topk_workspace_size(n_segments, k))
 
@@ -297,8 +358,8 @@ def pq_autotune(q: Tokens, d: PQDocs, cand: Candidates = None, reps: int = 3,
 
 
 def validate(d, q: Tokens = None, cand: Candidates = None, stream=None):
-    """Device-side checks of offsets, candidate ids, FP8 scales (Tokens docs)
-    or PQ codes (PQDocs docs); raises MaxSimError (status 5) naming the
+    """Device-side checks of offsets, candidate ids, FP8 scales (Tokens docs),
+    PQ codes (PQDocs docs) or centroid ids (ResidualDocs docs); raises MaxSimError (status 5) naming the
     violated rules. Synchronises the stream."""
     flags = torch.empty(1, dtype=torch.int32, device=d.offsets.device)
     qc = q.csr() if q is not None else None
@@ -308,6 +369,10 @@ def validate(d, q: Tokens = None, cand: Candidates = None, stream=None):
     if isinstance(d, PQDocs):
         pc = d.pq()
         _check(lib().maxsim_validate_pq(qp, ctypes.byref(pc), cp, _ptr(flags), _stream(stream)))
+    elif isinstance(d, ResidualDocs):
+        rc = d.res()
+        _check(lib().maxsim_validate_residual(qp, ctypes.byref(rc), cp, _ptr(flags),
+                                              _stream(stream)))
     else:
         dc = d.csr()
         _check(lib().maxsim_validate(qp, ctypes.byref(dc), cp, _ptr(flags), _stream(stream)))

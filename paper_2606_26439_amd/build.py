@@ -26,6 +26,8 @@ SOURCES = [("fused_inst.hip", f"fused_dt{t}", [f"-DFUSED_DT={t}"]) for t in rang
     # dot product is finite), so the maxima need no NaN canonicalisation
     ("pq.hip", "pq", ["-fno-honor-nans"]),
     ("pq_mfma.hip", "pq_mfma", ["-fno-honor-nans"]),
+    # the same holds for the residual scorer (finite table entries and codes)
+    ("residual.hip", "residual", ["-fno-honor-nans"]),
     ("topk.hip", "topk", []),
     ("quantize.hip", "quantize", []),
     ("probe.hip", "probe", []),

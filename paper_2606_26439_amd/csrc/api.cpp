@@ -643,6 +643,117 @@ maxsim_status maxsim_pq_autotune(const maxsim_csr* queries, const maxsim_pq_docs
 
 // --------------------------------------------------------------- top-k --
 
+// ------------------------------------------- residual-compressed docs --
+
+namespace {
+
+struct ResPlan {
+  ResParams P;
+  size_t ws = 0;
+};
+
+maxsim_status plan_residual(const maxsim_csr* q, const maxsim_residual_docs* d,
+                            const maxsim_candidates* cand, float* scores, ResPlan& pl) {
+  if (!q || !d) return fail(MAXSIM_EINVAL, "residual: NULL descriptor");
+  if (q->dtype != MAXSIM_F16) return fail(MAXSIM_EUNSUPPORTED, "residual: queries must be F16");
+  if (d->dim != 64 && d->dim != 128 && d->dim != 256)
+    return fail(MAXSIM_EUNSUPPORTED, "residual: dim %d must be 64, 128 or 256", d->dim);
+  if (q->dim != d->dim) return fail(MAXSIM_EINVAL, "residual: query dim != document dim");
+  if (d->nbits != 1 && d->nbits != 2 && d->nbits != 4)
+    return fail(MAXSIM_EUNSUPPORTED, "residual: nbits must be 1, 2 or 4");
+  if (q->n_sets < 0 || q->n_tokens < 0 || q->max_len < 0)
+    return fail(MAXSIM_EINVAL, "residual: negative query sizes");
+  if (q->max_len > 64) return fail(MAXSIM_EUNSUPPORTED, "residual: max_len exceeds 64 query tokens");
+  if (!q->offsets || (q->n_tokens > 0 && !q->tokens))
+    return fail(MAXSIM_EINVAL, "residual: NULL query arrays");
+  if (q->tokens && !aligned(q->tokens, 16))
+    return fail(MAXSIM_EINVAL, "residual: query tokens must be 16-byte aligned");
+  if (d->n_centroids < 1 || d->n_centroids > 0x7fffffffLL)
+    return fail(MAXSIM_EINVAL, "residual: n_centroids must be in [1, 2^31)");
+  if (!d->centroids || !d->weights || !d->offsets ||
+      (d->n_tokens > 0 && (!d->centroid_ids || !d->residuals)))
+    return fail(MAXSIM_EINVAL, "residual: NULL document arrays");
+  if (!aligned(d->centroids, 16) || !aligned(d->weights, 2) ||
+      (d->residuals && !aligned(d->residuals, 16)) ||
+      (d->centroid_ids && !aligned(d->centroid_ids, 4)) || !aligned(d->offsets, 8))
+    return fail(MAXSIM_EINVAL,
+                "residual: centroids and residuals must be 16-byte aligned (ids 4, offsets 8)");
+  if (d->n_docs < 0 || d->n_tokens < 0)
+    return fail(MAXSIM_EINVAL, "residual: negative document sizes");
+  int64_t n_pairs;
+  if (cand) {
+    if (!cand->offsets || cand->n_total < 0 || (cand->n_total > 0 && !cand->doc_ids))
+      return fail(MAXSIM_EINVAL, "residual: bad candidates");
+    n_pairs = cand->n_total;
+  } else {
+    n_pairs = q->n_sets * d->n_docs;
+  }
+  if (n_pairs > 0 && !scores) return fail(MAXSIM_EINVAL, "residual: scores is NULL");
+  ResParams& P = pl.P;
+  P.q_tok = q->tokens;
+  P.q_off = q->offsets;
+  P.n_q = q->n_sets;
+  P.n_qtok = q->n_tokens;
+  P.centroids = d->centroids;
+  P.n_centroids = d->n_centroids;
+  P.weights = d->weights;
+  P.ids = d->centroid_ids;
+  P.residuals = d->residuals;
+  P.d_off = d->offsets;
+  P.n_docs = d->n_docs;
+  P.cand_off = cand ? cand->offsets : nullptr;
+  P.cand_ids = cand ? cand->doc_ids : nullptr;
+  P.scores = scores;
+  P.table = nullptr;
+  P.dim = d->dim;
+  P.nbits = d->nbits;
+  P.nqb = pow2_at_least(std::max(1, (q->max_len + 15) / 16));
+  // about eight resident workgroups per CU over the launch, chunks of at
+  // least 64 documents
+  const int64_t per_query = cand ? (q->n_sets > 0 ? cand->n_total / q->n_sets : 0) : d->n_docs;
+  const int64_t want = (int64_t)device_info().cus * 8;
+  const int64_t nq = std::max<int64_t>(1, q->n_sets);
+  int64_t n_chunks = std::max<int64_t>(1, (want + nq - 1) / nq);
+  n_chunks = std::min<int64_t>(n_chunks, std::max<int64_t>(1, per_query / 64));
+  if (n_chunks * nq > 0x7fffffffLL) return fail(MAXSIM_EUNSUPPORTED, "residual: too many work items");
+  P.n_chunks = (int)n_chunks;
+  const size_t table = (size_t)d->n_centroids * (size_t)q->n_tokens * 4;
+  pl.ws = (table + 255) / 256 * 256;
+  return MAXSIM_OK;
+}
+
+}  // namespace
+
+size_t maxsim_residual_score_workspace_size(const maxsim_csr* queries,
+                                            const maxsim_residual_docs* docs,
+                                            const maxsim_candidates* cand) {
+  ResPlan pl;
+  std::string saved = g_err;
+  if (plan_residual(queries, docs, cand, (float*)1, pl)) {
+    g_err = saved;
+    return 0;
+  }
+  return pl.ws;
+}
+
+maxsim_status maxsim_residual_score(const maxsim_csr* queries, const maxsim_residual_docs* docs,
+                                    const maxsim_candidates* cand, float* scores,
+                                    void* workspace, size_t ws_bytes, maxsim_stream_t stream) {
+  ResPlan pl;
+  maxsim_status st = plan_residual(queries, docs, cand, scores, pl);
+  if (st) return st;
+  if (pl.ws > 0 && (!workspace || ws_bytes < pl.ws))
+    return fail(MAXSIM_EWORKSPACE, "residual: workspace needs %zu bytes", pl.ws);
+  if (pl.ws > 0 && !aligned(workspace, 16))
+    return fail(MAXSIM_EINVAL, "residual: workspace must be 16-byte aligned");
+  const int64_t n_pairs = cand ? cand->n_total : queries->n_sets * docs->n_docs;
+  if (n_pairs == 0) return MAXSIM_OK;
+  pl.P.table = (float*)workspace;
+  hipError_t e = launch_residual(pl.P, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "residual launch");
+  return MAXSIM_OK;
+}
+
 size_t maxsim_topk_workspace_size(int64_t n_segments, int32_t k) {
   if (n_segments < 0 || k < 1 || k > 1024) return 0;
   return topk_ws_bytes(n_segments, k);
@@ -745,6 +856,26 @@ maxsim_status maxsim_validate_pq(const maxsim_csr* queries, const maxsim_pq_docs
   return MAXSIM_OK;
 }
 
+maxsim_status maxsim_validate_residual(const maxsim_csr* queries,
+                                       const maxsim_residual_docs* docs,
+                                       const maxsim_candidates* cand, int32_t* flags,
+                                       maxsim_stream_t stream) {
+  if (!flags) return fail(MAXSIM_EINVAL, "validate: flags is NULL");
+  if (!docs || !docs->offsets || docs->n_docs < 0 || docs->n_tokens < 0 ||
+      (docs->n_tokens > 0 && !docs->centroid_ids) || docs->n_centroids < 1)
+    return fail(MAXSIM_EINVAL, "validate: bad residual descriptor");
+  maxsim_status st;
+  if (queries && (st = check_csr(queries, "queries", true))) return st;
+  if ((st = check_cand_desc(queries, cand))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  st = validate_common(queries, docs->offsets, docs->n_docs, docs->n_tokens, cand, flags, s);
+  if (st) return st;
+  hipError_t e = launch_check_ids(docs->centroid_ids, docs->n_tokens, docs->n_centroids,
+                                  MAXSIM_CHECK_CENTROID_IDS, flags, s);
+  if (e != hipSuccess) return hip_fail(e, "validate launch");
+  return MAXSIM_OK;
+}
+
 maxsim_status maxsim_check(const int32_t* flags, maxsim_stream_t stream) {
   if (!flags) return fail(MAXSIM_EINVAL, "check: flags is NULL");
   int32_t v = 0;
@@ -754,9 +885,9 @@ maxsim_status maxsim_check(const int32_t* flags, maxsim_stream_t stream) {
   if (v == 0) return MAXSIM_OK;
   static const char* names[] = {"document offsets",  "query offsets", "query longer than max_len",
                                 "candidate offsets", "candidate ids", "FP8 scales",
-                                "PQ codes"};
+                                "PQ codes",          "centroid ids"};
   std::string msg = "device check failed:";
-  for (int b = 0; b < 7; ++b)
+  for (int b = 0; b < 8; ++b)
     if (v & (1 << b)) msg += std::string(" [") + names[b] + "]";
   return fail(MAXSIM_EDEVCHECK, "%s", msg.c_str());
 }

@@ -88,6 +88,31 @@ hipError_t launch_pq(const PqParams& P, int max_nq, hipStream_t s);
 // lds = M * K * dsub * 2 bytes; nqb in {1, 2, 4, 8} with nqb * M * dsub <= 1024.
 hipError_t launch_pq_mfma(const PqParams& P, size_t lds, hipStream_t s);
 
+// ---- residual-compressed documents ----
+struct ResParams {
+  const void* q_tok;  // F16 [n_qtok, dim]
+  const int64_t* q_off;
+  int64_t n_q;
+  int64_t n_qtok;         // q_off[n_q] (host copy): row length of `table`
+  const void* centroids;  // F16 [n_centroids, dim]
+  int64_t n_centroids;
+  const void* weights;  // F16 [2^nbits]
+  const int32_t* ids;   // [T] centroid id per document token
+  const uint8_t* residuals;  // [T, dim * nbits / 8] packed codes
+  const int64_t* d_off;
+  int64_t n_docs;
+  const int64_t* cand_off;
+  const int32_t* cand_ids;
+  float* scores;
+  float* table;  // workspace: [n_centroids, n_qtok] FP32
+  int32_t dim;    // 64, 128 or 256
+  int32_t nbits;  // 1, 2 or 4
+  int32_t nqb;    // 16-column query blocks (1, 2, 4)
+  int32_t n_chunks;  // document-range chunks per query
+};
+// Builds the centroid-query table, then scores (grid n_q * n_chunks).
+hipError_t launch_residual(const ResParams& P, hipStream_t s);
+
 // ---- top-k ----
 hipError_t launch_topk(const float* scores, const int64_t* seg_off, int64_t n_seg, int64_t n_total,
                        const int32_t* ids, int k, float* out_scores, int32_t* out_ids, void* ws,

@@ -100,3 +100,38 @@ def test_validate_rejects_bad_host_arguments():
     bad = _csr(dim=96)
     assert L.maxsim_validate(None, ctypes.byref(bad), None, ctypes.c_void_p(16), None) == 2
     assert L.maxsim_validate_pq(None, None, None, ctypes.c_void_p(16), None) == 1
+
+
+def _res(dim=128, nbits=2, n_c=1000, centroids=16, weights=16, ids=16, residuals=16,
+         n_docs=10, n_tokens=100):
+    return B.Residual(dim, nbits, n_c, centroids, weights, ids, residuals, 16, n_docs, n_tokens)
+
+
+@pytest.mark.parametrize("q,d,code", [
+    (dict(dim=96), dict(dim=96), 2),        # dim not 64, 128 or 256
+    (dict(), dict(nbits=3), 2),             # residual width
+    (dict(dtype=1), dict(), 2),             # queries must be F16
+    (dict(dim=256), dict(), 1),             # dims differ
+    (dict(), dict(n_c=0), 1),               # no centroids
+    (dict(), dict(residuals=8), 1),         # misaligned residual rows
+    (dict(), dict(centroids=None), 1),      # NULL centroids
+    (dict(max_len=65), dict(), 2),          # too many query tokens
+])
+def test_residual_rejects_bad_arguments(q, d, code):
+    L = M.lib()
+    qc, rc = _csr(**q), _res(**d)
+    st = L.maxsim_residual_score(ctypes.byref(qc), ctypes.byref(rc), None, ctypes.c_void_p(16),
+                                 ctypes.c_void_p(256), 1 << 30, None)
+    assert st == code, L.maxsim_last_error()
+
+
+def test_residual_workspace_is_the_centroid_table():
+    L = M.lib()
+    qc = _csr(n_tokens=37, max_len=37)
+    rc = _res(n_c=1001)
+    need = L.maxsim_residual_score_workspace_size(ctypes.byref(qc), ctypes.byref(rc), None)
+    assert need == (1001 * 37 * 4 + 255) // 256 * 256
+    assert L.maxsim_residual_score(ctypes.byref(qc), ctypes.byref(rc), None, ctypes.c_void_p(16),
+                                   ctypes.c_void_p(256), need - 1, None) == 3
+    assert L.maxsim_validate_residual(None, ctypes.byref(rc), None, None, None) == 1
+    assert L.maxsim_validate_residual(None, None, None, ctypes.c_void_p(16), None) == 1
