@@ -505,6 +505,7 @@ def bench_residual(n_docs=1_000_000, nq=32, dim=128, n_centroids=1 << 17, nbits_
         w_np = W.residual_weights(nbits)
         D = M.ResidualDocs(cen, torch.from_numpy(w_np).cuda(), ids, res, d_off, nbits)
         ws = torch.empty(M.residual_workspace_bytes(Q, D), dtype=torch.uint8, device="cuda")
+        tune = M.residual_autotune(Q, D, reps=5)
         med, mean, std = time_fn(lambda: M.residual_score(Q, D, out=sc, workspace=ws), 20, 3)
         want = oracle.residual_decode_score(q_np.astype(np.float64), q_off_np, ids_s,
                                             res[rows_t].cpu().numpy(), cen_np.astype(np.float64),
@@ -520,14 +521,31 @@ def bench_residual(n_docs=1_000_000, nq=32, dim=128, n_centroids=1 << 17, nbits_
                "alg_hbm_bytes": hbm, "hbm_GBps": hbm / (med * 1e-3) / 1e9,
                "hbm_frac": hbm / (med * 1e-3) / HBM_PEAK,
                "table_gather_GBps": gather / (med * 1e-3) / 1e9,
-               "sampled_max_rel_err_vs_decode_then_score": err}
+               "sampled_max_rel_err_vs_decode_then_score": err,
+               "pipeline_trials_ms": tune["trials"], "pipe": tune["best"]["pipe"]}
         out["variants"].append(rec)
         log(f"[bench] residual {nbits}-bit: {med:.3f} ms, {rec['docs_per_s'] / 1e6:.0f} M docs/s, "
             f"HBM {rec['hbm_GBps']:.0f} GB/s, table gathers {rec['table_gather_GBps']:.0f} GB/s, "
-            f"err {err:.1e}")
+            f"err {err:.1e}, pipeline trials {tune['trials']}")
         del res, D, ws
         torch.cuda.empty_cache()
-    del ids, cen, sc
+    # table size: the gathered table is n_centroids x 32 x 4 B (16 MB at 2^17);
+    # how the time depends on it (2-bit residuals, same documents)
+    res = W.residual_codes_gpu(T, dim, 2, seed=6)
+    w2 = torch.from_numpy(W.residual_weights(2)).cuda()
+    out["centroid_sweep"] = []
+    for n_c in (1 << 12, 1 << 14, 1 << 16, 1 << 18):
+        cen_c = torch.from_numpy(W.residual_centroids(n_c, dim, seed=5)).cuda()
+        ids_c = W.residual_ids_gpu(T, n_c, seed=6)
+        D = M.ResidualDocs(cen_c, w2, ids_c, res, d_off, 2)
+        ws = torch.empty(M.residual_workspace_bytes(Q, D), dtype=torch.uint8, device="cuda")
+        med, _, _ = time_fn(lambda: M.residual_score(Q, D, out=sc, workspace=ws), 20, 3)
+        out["centroid_sweep"].append({"n_centroids": n_c, "table_MB": n_c * nq * 4 / 1e6,
+                                      "ms_median": med, "docs_per_s": n_docs / (med * 1e-3)})
+        log(f"[bench] residual 2-bit, {n_c} centroids ({n_c * nq * 4 / 1e6:.1f} MB table): "
+            f"{med:.3f} ms")
+        del cen_c, ids_c, D, ws
+    del ids, cen, sc, res
     torch.cuda.empty_cache()
     return out
 

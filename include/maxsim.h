@@ -129,7 +129,7 @@ typedef struct {
  * where code(t, k) is the nbits-wide field at bit k * nbits of row t of
  * `residuals` (row_bytes = dim * nbits / 8; fields fill each byte from its
  * least significant bit up).
- *   dim in {64, 128, 256}; nbits in {1, 2, 4}; n_centroids >= 1.
+ *   dim in {64, 128, 256}; nbits in {1, 2, 4}; 1 <= n_centroids < 2^24.
  *   centroids    [n_centroids, dim] F16, 16-byte aligned.
  *   weights      [2^nbits] F16: the residual value of each code.
  *   centroid_ids [n_tokens] int32; ids outside [0, n_centroids) are the
@@ -218,10 +218,13 @@ maxsim_status maxsim_pq_score(const maxsim_csr* queries, const maxsim_pq_docs* d
  * token's id and packed residual once, gathers P[id_j, i], decodes the
  * residual in registers and adds q_i . r_j before the max over tokens and the
  * sum over query tokens. Decoded vectors are never written.
- *   queries    F16, same dim, max_len <= 64.
+ *   queries    F16, same dim, max_len <= 64. n_centroids and
+ *              queries->n_tokens below 2^24 and (n_centroids + 1) *
+ *              queries->n_tokens below 2^32 (else MAXSIM_EUNSUPPORTED).
  *   cand       as for maxsim_score.
- *   workspace  maxsim_residual_score_workspace_size() bytes
- *              (n_centroids * queries->n_tokens * 4, rounded up to 256).
+ *   workspace  maxsim_residual_score_workspace_size() bytes: the table plus
+ *              one row of zeros, (n_centroids + 1) * queries->n_tokens * 4,
+ *              rounded up to 256.
  */
 size_t maxsim_residual_score_workspace_size(const maxsim_csr* queries,
                                             const maxsim_residual_docs* docs,
@@ -259,8 +262,8 @@ maxsim_status maxsim_autotune(const maxsim_csr* queries, const maxsim_csr* docs,
                               const maxsim_candidates* cand, float* scores, void* workspace,
                               size_t ws_bytes, maxsim_stream_t stream, int32_t reps,
                               const char* cache_path, char* report, size_t report_len);
-/* Loads tuned configurations written by maxsim_autotune or
- * maxsim_pq_autotune (missing file: OK, no-op). */
+/* Loads tuned configurations written by maxsim_autotune,
+ * maxsim_pq_autotune or maxsim_residual_autotune (missing file: OK, no-op). */
 maxsim_status maxsim_load_tune_cache(const char* cache_path);
 
 /*
@@ -281,6 +284,22 @@ maxsim_status maxsim_pq_autotune(const maxsim_csr* queries, const maxsim_pq_docs
                                  const maxsim_candidates* cand, float* scores, void* workspace,
                                  size_t ws_bytes, maxsim_stream_t stream, int32_t reps,
                                  const char* cache_path, char* report, size_t report_len);
+
+/*
+ * Residual scorer tuning: the fused residual kernel keeps a ring of document
+ * tiles in flight (centroid ids loaded several tiles ahead of the table
+ * gathers they address, which run ahead of the matrix work); this call times
+ * each ring shape on the given problem (synchronises `stream`), keeps the
+ * fastest for the key (nbits, dim, query blocks, candidates or not),
+ * rewrites cache_path (if not NULL) with every tuned key and writes a
+ * one-line JSON report. Workspace as for maxsim_residual_score.
+ */
+maxsim_status maxsim_residual_autotune(const maxsim_csr* queries,
+                                       const maxsim_residual_docs* docs,
+                                       const maxsim_candidates* cand, float* scores,
+                                       void* workspace, size_t ws_bytes, maxsim_stream_t stream,
+                                       int32_t reps, const char* cache_path, char* report,
+                                       size_t report_len);
 
 /*
  * Device-side input checks. The scoring calls trust what lives in device

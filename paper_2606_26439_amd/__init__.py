@@ -8,6 +8,7 @@ loop built on it. PyTorch provides device memory and streams only.
 """
 from ._binding import (DTYPES, ELEM_BYTES, Candidates, MaxSimError, PQDocs,  # noqa: F401
                        ResidualDocs, Tokens, autotune, default_tune_cache, lib,
-                       load_tune_cache, pq_autotune, pq_score, quantize, residual_score,
+                       load_tune_cache, pq_autotune, pq_score, quantize, residual_autotune,
+                       residual_score,
                        residual_workspace_bytes, score, score_unfused, stream_probe, topk,
                        topk_workspace_bytes, unfused_workspace_bytes, validate)

@@ -97,6 +97,9 @@ def lib():
     L.maxsim_pq_autotune.argtypes = [_P(CSR), _P(PQ), _P(Cand), _vp, _vp, ctypes.c_size_t, _vp,
                                      ctypes.c_int32, ctypes.c_char_p, ctypes.c_char_p,
                                      ctypes.c_size_t]
+    L.maxsim_residual_autotune.argtypes = [_P(CSR), _P(Residual), _P(Cand), _vp, _vp,
+                                           ctypes.c_size_t, _vp, ctypes.c_int32, ctypes.c_char_p,
+                                           ctypes.c_char_p, ctypes.c_size_t]
     L.maxsim_validate.argtypes = [_P(CSR), _P(CSR), _P(Cand), _vp, _vp]
     L.maxsim_validate_pq.argtypes = [_P(CSR), _P(PQ), _P(Cand), _vp, _vp]
     L.maxsim_validate_residual.argtypes = [_P(CSR), _P(Residual), _P(Cand), _vp, _vp]
@@ -108,7 +111,7 @@ def lib():
                  "maxsim_topk", "maxsim_autotune", "maxsim_pq_autotune",
                  "maxsim_load_tune_cache", "maxsim_stream_probe", "maxsim_validate",
                  "maxsim_validate_pq", "maxsim_check", "maxsim_residual_score",
-                 "maxsim_validate_residual"):
+                 "maxsim_validate_residual", "maxsim_residual_autotune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     # launch shapes tuned on an MI355X for the shipped key set (missing: defaults)
@@ -354,6 +357,25 @@ def pq_autotune(q: Tokens, d: PQDocs, cand: Candidates = None, reps: int = 3,
     _check(lib().maxsim_pq_autotune(ctypes.byref(qc), ctypes.byref(pc), ccp, _ptr(out), _ptr(ws),
                                     ws.numel(), _stream(stream), reps,
                                     cache_path.encode() if cache_path else None, buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
+def residual_autotune(q: Tokens, d: ResidualDocs, cand: Candidates = None, reps: int = 5,
+                      cache_path: str = None, stream=None) -> dict:
+    """Times the residual scorer's load-pipeline shapes on this problem and
+    keeps the fastest for its key."""
+    n = _n_pairs(q, d.n_docs, cand)
+    out = torch.empty(max(n, 1), dtype=torch.float32, device=d.offsets.device)
+    qc, rc = q.csr(), d.res()
+    cc = cand.c() if cand is not None else None
+    ccp = ctypes.byref(cc) if cc is not None else None
+    need = int(lib().maxsim_residual_score_workspace_size(ctypes.byref(qc), ctypes.byref(rc), ccp))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=d.offsets.device)
+    buf = ctypes.create_string_buffer(1 << 12)
+    _check(lib().maxsim_residual_autotune(ctypes.byref(qc), ctypes.byref(rc), ccp, _ptr(out),
+                                          _ptr(ws), ws.numel(), _stream(stream), reps,
+                                          cache_path.encode() if cache_path else None, buf,
+                                          len(buf)))
     return json.loads(buf.value.decode())
 
 

@@ -122,6 +122,19 @@ struct PqCfg {
 };
 std::map<PqKey, PqCfg> g_pq_tuned;
 
+// Residual scorer: load-pipeline variant per (nbits, dim, query blocks,
+// candidates or not).
+struct ResKey {
+  int nbits, dim, nqb, cand;
+  bool operator<(const ResKey& o) const {
+    return std::tie(nbits, dim, nqb, cand) < std::tie(o.nbits, o.dim, o.nqb, o.cand);
+  }
+};
+struct ResCfg {
+  int pipe = -1;  // -1: automatic
+};
+std::map<ResKey, ResCfg> g_res_tuned;
+
 // Untuned keys: document tiles staged through LDS (the faster form measured on
 // MI355X for every element type but FP32) when the ring fits beside the query
 // block, else register-direct.
@@ -288,6 +301,15 @@ std::string cfg_json_all() {
              "\"stage\":%d,\"rows\":%d}",
              first ? "" : ",", kv.first.dt, kv.first.dim, kv.first.nqb, kv.second.pf, kv.second.nw,
              kv.second.wg_per_cu, kv.second.stage, kv.second.rows);
+    out += b;
+    first = false;
+  }
+  for (auto& kv : g_res_tuned) {
+    char b[160];
+    snprintf(b, sizeof b, "%s{\"residual\":1,\"nbits\":%d,\"dim\":%d,\"nqb\":%d,\"cand\":%d,"
+             "\"pipe\":%d}",
+             first ? "" : ",", kv.first.nbits, kv.first.dim, kv.first.nqb, kv.first.cand,
+             kv.second.pipe);
     out += b;
     first = false;
   }
@@ -652,8 +674,13 @@ struct ResPlan {
   size_t ws = 0;
 };
 
+// Untuned keys: ids two tiles ahead of the table gathers, which run two tiles
+// ahead of the compute.
+constexpr int RES_DEFAULT_PIPE = 2;
+
 maxsim_status plan_residual(const maxsim_csr* q, const maxsim_residual_docs* d,
-                            const maxsim_candidates* cand, float* scores, ResPlan& pl) {
+                            const maxsim_candidates* cand, float* scores, ResPlan& pl,
+                            int force_pipe = -1) {
   if (!q || !d) return fail(MAXSIM_EINVAL, "residual: NULL descriptor");
   if (q->dtype != MAXSIM_F16) return fail(MAXSIM_EUNSUPPORTED, "residual: queries must be F16");
   if (d->dim != 64 && d->dim != 128 && d->dim != 256)
@@ -668,8 +695,7 @@ maxsim_status plan_residual(const maxsim_csr* q, const maxsim_residual_docs* d,
     return fail(MAXSIM_EINVAL, "residual: NULL query arrays");
   if (q->tokens && !aligned(q->tokens, 16))
     return fail(MAXSIM_EINVAL, "residual: query tokens must be 16-byte aligned");
-  if (d->n_centroids < 1 || d->n_centroids > 0x7fffffffLL)
-    return fail(MAXSIM_EINVAL, "residual: n_centroids must be in [1, 2^31)");
+  if (d->n_centroids < 1) return fail(MAXSIM_EINVAL, "residual: n_centroids must be >= 1");
   if (!d->centroids || !d->weights || !d->offsets ||
       (d->n_tokens > 0 && (!d->centroid_ids || !d->residuals)))
     return fail(MAXSIM_EINVAL, "residual: NULL document arrays");
@@ -716,9 +742,25 @@ maxsim_status plan_residual(const maxsim_csr* q, const maxsim_residual_docs* d,
   int64_t n_chunks = std::max<int64_t>(1, (want + nq - 1) / nq);
   n_chunks = std::min<int64_t>(n_chunks, std::max<int64_t>(1, per_query / 64));
   if (n_chunks * nq > 0x7fffffffLL) return fail(MAXSIM_EUNSUPPORTED, "residual: too many work items");
+  // a work item's span of documents (or candidate positions) stays in 32 bits
+  const int64_t span_bound = (cand ? cand->n_total : d->n_docs) / n_chunks + 1;
+  if (span_bound >= 0x7fffffffLL - 64)
+    return fail(MAXSIM_EUNSUPPORTED, "residual: too many documents per work item");
   P.n_chunks = (int)n_chunks;
-  const size_t table = (size_t)d->n_centroids * (size_t)q->n_tokens * 4;
+  if (d->n_centroids >= (1 << 24) || q->n_tokens >= (1 << 24) ||
+      (uint64_t)(d->n_centroids + 1) * (uint64_t)q->n_tokens >= (1ull << 32))
+    return fail(MAXSIM_EUNSUPPORTED,
+                "residual: n_centroids and query tokens below 2^24, and (n_centroids + 1) x "
+                "query tokens below 2^32 table entries");
+  const size_t table = (size_t)(d->n_centroids + 1) * (size_t)q->n_tokens * 4;
   pl.ws = (table + 255) / 256 * 256;
+  int pipe = force_pipe;
+  if (pipe < 0) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_res_tuned.find(ResKey{d->nbits, d->dim, P.nqb, cand ? 1 : 0});
+    pipe = it == g_res_tuned.end() ? RES_DEFAULT_PIPE : it->second.pipe;
+  }
+  P.pipe = pipe;
   return MAXSIM_OK;
 }
 
@@ -751,6 +793,74 @@ maxsim_status maxsim_residual_score(const maxsim_csr* queries, const maxsim_resi
   pl.P.table = (float*)workspace;
   hipError_t e = launch_residual(pl.P, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "residual launch");
+  return MAXSIM_OK;
+}
+
+maxsim_status maxsim_residual_autotune(const maxsim_csr* queries,
+                                       const maxsim_residual_docs* docs,
+                                       const maxsim_candidates* cand, float* scores,
+                                       void* workspace, size_t ws_bytes, maxsim_stream_t stream,
+                                       int32_t reps, const char* cache_path, char* report,
+                                       size_t report_len) {
+  ResPlan probe;
+  maxsim_status st = plan_residual(queries, docs, cand, scores, probe);
+  if (st) return st;
+  if (probe.ws > 0 && (!workspace || ws_bytes < probe.ws))
+    return fail(MAXSIM_EWORKSPACE, "residual autotune: workspace needs %zu bytes", probe.ws);
+  const int64_t n_pairs = cand ? cand->n_total : queries->n_sets * docs->n_docs;
+  if (reps < 1) reps = 1;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(MAXSIM_EHIP, "residual autotune: event creation failed");
+  const ResKey key{docs->nbits, docs->dim, probe.P.nqb, cand ? 1 : 0};
+  std::string rep = "{\"residual\":1,\"nbits\":" + std::to_string(key.nbits) +
+                    ",\"dim\":" + std::to_string(key.dim) + ",\"nqb\":" +
+                    std::to_string(key.nqb) + ",\"cand\":" + std::to_string(key.cand) +
+                    ",\"trials\":[";
+  float best_ms = 1e30f;
+  int best = RES_DEFAULT_PIPE;
+  bool first = true;
+  for (int pipe = 0; pipe < RES_PIPES && n_pairs > 0; ++pipe) {
+    ResPlan pl;
+    if (plan_residual(queries, docs, cand, scores, pl, pipe)) continue;
+    pl.P.table = (float*)workspace;
+    if (launch_residual(pl.P, s) != hipSuccess) continue;
+    (void)hipEventRecord(e0, s);
+    bool ok = true;
+    for (int r = 0; r < reps && ok; ++r) ok = launch_residual(pl.P, s) == hipSuccess;
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess || !ok) continue;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= reps;
+    char b[96];
+    snprintf(b, sizeof b, "%s{\"pipe\":%d,\"ms\":%.5f}", first ? "" : ",", pipe, ms);
+    rep += b;
+    first = false;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = pipe;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  char b[96];
+  snprintf(b, sizeof b, "],\"best\":{\"pipe\":%d,\"ms\":%.5f}}", best, best_ms);
+  rep += b;
+  std::string all;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_res_tuned[key] = ResCfg{best};
+    all = cfg_json_all();
+  }
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "wb");
+    if (!f) return fail(MAXSIM_EINVAL, "residual autotune: cannot write %s", cache_path);
+    fputs(all.c_str(), f);
+    fclose(f);
+  }
+  if (report && report_len > 0) snprintf(report, report_len, "%s", rep.c_str());
   return MAXSIM_OK;
 }
 
@@ -948,6 +1058,19 @@ maxsim_status maxsim_load_tune_cache(const char* path) {
         json_int(obj.c_str(), "variant", c.variant) && json_int(obj.c_str(), "nqb", c.nqb)) {
       if ((c.variant == 0 || c.variant == 1) && (c.nqb >= 0 && c.nqb <= 8)) g_pq_tuned[k] = c;
     }
+    pos = end;
+  }
+  pos = 0;
+  while ((pos = txt.find("{\"residual\"", pos)) != std::string::npos) {
+    size_t end = txt.find('}', pos);
+    if (end == std::string::npos) break;
+    std::string obj = txt.substr(pos, end - pos + 1);
+    ResKey k{};
+    ResCfg c{};
+    if (json_int(obj.c_str(), "nbits", k.nbits) && json_int(obj.c_str(), "dim", k.dim) &&
+        json_int(obj.c_str(), "nqb", k.nqb) && json_int(obj.c_str(), "cand", k.cand) &&
+        json_int(obj.c_str(), "pipe", c.pipe) && c.pipe >= 0 && c.pipe < RES_PIPES)
+      g_res_tuned[k] = c;
     pos = end;
   }
   return MAXSIM_OK;

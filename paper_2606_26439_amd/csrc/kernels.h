@@ -104,12 +104,16 @@ struct ResParams {
   const int64_t* cand_off;
   const int32_t* cand_ids;
   float* scores;
-  float* table;  // workspace: [n_centroids, n_qtok] FP32
+  float* table;  // workspace: [n_centroids + 1, n_qtok] FP32 (last row zeros)
+  const char* zero_row;  // set by launch_residual: 1 KiB of device zeros
   int32_t dim;    // 64, 128 or 256
   int32_t nbits;  // 1, 2 or 4
   int32_t nqb;    // 16-column query blocks (1, 2, 4)
   int32_t n_chunks;  // document-range chunks per query
+  int32_t pipe;      // load-pipeline variant, 0 .. RES_PIPES - 1
+  int32_t pad;
 };
+constexpr int RES_PIPES = 4;
 // Builds the centroid-query table, then scores (grid n_q * n_chunks).
 hipError_t launch_residual(const ResParams& P, hipStream_t s);
 

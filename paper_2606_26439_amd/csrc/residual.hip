@@ -20,6 +20,9 @@
 // query operand uses the same order, so every product pairs equal columns,
 // and a lane's residual codes for all k-steps are one contiguous
 // dim * NBITS / 32-byte piece of the packed row.
+#include <map>
+#include <mutex>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -34,7 +37,7 @@ __global__ __launch_bounds__(256) void centroid_table_kernel(ResParams P) {
   const int r = lane & 15, g = lane >> 4;
   const int64_t c0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
   const int64_t n_c = P.n_centroids;
-  if (c0 >= n_c) return;  // uniform per wave
+  if (c0 > n_c) return;  // uniform per wave
   const int64_t cr = c0 + r < n_c ? c0 + r : n_c - 1;
   const _Float16* crow = (const _Float16*)P.centroids + cr * DIM + g * (DIM / 4);
   f16x8 a[NKS];
@@ -53,14 +56,17 @@ __global__ __launch_bounds__(256) void centroid_table_kernel(ResParams P) {
       acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[s], __builtin_bit_cast(f16x8, v), acc, 0, 0,
                                                    0);
     }
-    // lane holds centroids c0 + 4g + v, query token j
+    // lane holds centroids c0 + 4g + v, query token j; row n_c is all zeros
+    // (the entry that lanes without a live query column read)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t c = c0 + 4 * g + v;
-      if (live && c < n_c) P.table[c * nqt + j] = acc[v];
+      if (live && c <= n_c) P.table[c * nqt + j] = c < n_c ? acc[v] : 0.f;
     }
   }
 }
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // Residual bytes of one lane for one token, as 32-bit words.
 template <int RB>
@@ -69,17 +75,17 @@ struct ResWords {
   uint32_t w[N];
   __device__ void load(const uint8_t* p) {
     if constexpr (RB == 2) {
-      w[0] = *(const uint16_t*)p;
+      w[0] = __builtin_nontemporal_load((const uint16_t*)p);
     } else if constexpr (RB == 4) {
-      w[0] = *(const uint32_t*)p;
+      w[0] = __builtin_nontemporal_load((const uint32_t*)p);
     } else if constexpr (RB == 8) {
-      const uint2 v = *(const uint2*)p;
+      const u32x2 v = __builtin_nontemporal_load((const u32x2*)p);
       w[0] = v.x;
       w[1] = v.y;
     } else {
 #pragma unroll
       for (int h = 0; h < RB / 16; ++h) {
-        const u32x4 v = *(const u32x4*)(p + 16 * h);
+        const u32x4 v = __builtin_nontemporal_load((const u32x4*)(p + 16 * h));
         w[4 * h] = v.x;
         w[4 * h + 1] = v.y;
         w[4 * h + 2] = v.z;
@@ -97,7 +103,7 @@ struct ResWords {
   }
 };
 
-template <int NBITS, int NKS, int NQB, int NW>
+template <int NBITS, int NKS, int NQB, int NW, int PI, int PR>
 __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
   constexpr int DIM = NKS * 32;
   constexpr int RB = NKS * NBITS;  // residual bytes per lane per token
@@ -118,10 +124,12 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
     p0 = (P.n_docs * chunk) / P.n_chunks;
     p1 = (P.n_docs * (chunk + 1)) / P.n_chunks;
   } else {
-    const int64_t c0 = P.cand_off[a], c1 = P.cand_off[a + 1];
+    const int64_t c0 = sload_i64(P.cand_off, a), c1 = sload_i64(P.cand_off, a + 1);
     p0 = c0 + ((c1 - c0) * chunk) / P.n_chunks;
     p1 = c0 + ((c1 - c0) * (chunk + 1)) / P.n_chunks;
   }
+  p0 = uniform64(p0);
+  p1 = uniform64(p1);
   if (p0 >= p1) return;  // uniform for the whole workgroup
 
   // LUT: entry b holds the residual values of the FPB fields of byte b,
@@ -132,16 +140,18 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
   }
 
   // query operand: block nb holds tokens nb*16 + r of query a (zero past its end)
-  const int64_t qa0 = P.q_off[a];
-  const int nq = (int)(P.q_off[a + 1] - qa0);
+  const int64_t qa0 = uniform64(sload_i64(P.q_off, a));
+  const int nq = uniform((int)(sload_i64(P.q_off, a + 1) - qa0));
   f16x8 qb[NQB][NKS];
   int64_t qcol[NQB];  // table column of this lane's query token per block
+  uint32_t qcol32[NQB];
   bool qlive[NQB];
 #pragma unroll
   for (int nb = 0; nb < NQB; ++nb) {
     const int t = nb * 16 + r;
     qlive[nb] = t < nq;
     qcol[nb] = qa0 + (qlive[nb] ? t : 0);
+    qcol32[nb] = (uint32_t)qcol[nb];
     const _Float16* qrow = (const _Float16*)P.q_tok + qcol[nb] * DIM + g * (DIM / 4);
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
@@ -159,15 +169,18 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
   auto doc_of = [&](int64_t pp) -> int64_t {
     return has_cand ? (int64_t)sload_i32(P.cand_ids, pp) : pp;
   };
-  int64_t cp = p0 + wave;
+  // positions relative to p0 in 32 bits (the host keeps a span below 2^31),
+  // so the cursor tests are scalar compares
+  const int span = (int)(p1 - p0);
+  int cp = wave;
   int64_t ct0 = 0, nx_s = 0, nx_e = 0;
   int cnd = 0, ctile = 0;
-  if (cp < p1) {
-    const int64_t b0 = doc_of(cp);
+  if (cp < span) {
+    const int64_t b0 = doc_of(p0 + cp);
     ct0 = sload_i64(P.d_off, b0);
     cnd = (int)(sload_i64(P.d_off, b0 + 1) - ct0);
-    if (cp + NW < p1) {
-      const int64_t b1 = doc_of(cp + NW);
+    if (cp + NW < span) {
+      const int64_t b1 = doc_of(p0 + cp + NW);
       nx_s = sload_i64(P.d_off, b1);
       nx_e = sload_i64(P.d_off, b1 + 1);
     }
@@ -178,8 +191,8 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
     int rows, flags;
   };
   auto next_tile = [&]() -> Tile {
-    Tile t{cp, 0, 1, 0};
-    if (cp < p1) {
+    Tile t{p0 + cp, 0, 1, 0};
+    if (cp < span) {
       if (cnd == 0) {
         t.flags = F_VALID | F_EMPTY;
       } else {
@@ -192,8 +205,8 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
         ctile = 0;
         ct0 = nx_s;
         cnd = (int)(nx_e - nx_s);
-        if (cp + NW < p1) {
-          const int64_t b1 = doc_of(cp + NW);
+        if (cp + NW < span) {
+          const int64_t b1 = doc_of(p0 + cp + NW);
           nx_s = sload_i64(P.d_off, b1);
           nx_e = sload_i64(P.d_off, b1 + 1);
         }
@@ -205,35 +218,47 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
   };
 
   const uint32_t max_c = (uint32_t)(P.n_centroids - 1);
-  // centroid ids of accumulator rows 4g .. 4g+3 (clamped to the tile's rows;
-  // an id outside the table is clamped too, so a bad id cannot read outside it)
-  auto load_ids = [&](const Tile& t, uint32_t (&id)[4]) {
+  // The host keeps n_centroids + 1 and n_qtok below 2^24 and the table below
+  // 2^32 entries, so table indices are 24 x 24-bit products in 32 bits.
+  // Table row n_centroids is all zeros: a lane whose query column is not live
+  // reads it (multiplier 0, base the zero row's first entry), and so does
+  // every lane of a tile without tokens (id n_centroids).
+  const uint32_t nqt = (uint32_t)P.n_qtok;
+  const uint32_t zero_idx = (uint32_t)P.n_centroids * nqt;
+  uint32_t qmul[NQB], qbase[NQB];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) id[v] = 0;
-    if (t.flags & F_TOK) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 4 * g + v < t.rows ? 4 * g + v : t.rows - 1;
-        const uint32_t c = (uint32_t)P.ids[t.tok0 + row];
-        id[v] = c < max_c ? c : max_c;
-      }
-    }
+  for (int nb = 0; nb < NQB; ++nb) {
+    qmul[nb] = qlive[nb] ? nqt : 0u;
+    qbase[nb] = qlive[nb] ? qcol32[nb] : zero_idx;
+  }
+  const char* zrow = P.zero_row;
+  // Every tile issues the same loads (a tile without tokens reads the zero
+  // row instead), so the count of loads in flight is the same on every path
+  // and the compiler's waits stay exact across the ring. The document
+  // streams are read once: non-temporal loads keep them from displacing the
+  // centroid table in the caches.
+  // Centroid id of tile row r (clamped to the tile's rows; clamped to the
+  // table where it is used, so a bad id cannot read outside it).
+  auto load_ids = [&](const Tile& t, uint32_t& id) {
+    const int row = r < t.rows ? r : t.rows - 1;
+    const int32_t* src = (t.flags & F_TOK) ? P.ids + t.tok0 + row : (const int32_t*)zrow;
+    id = (uint32_t)__builtin_nontemporal_load(src);
   };
-  auto load_rest = [&](const Tile& t, const uint32_t (&id)[4], ResWords<RB>& rw,
-                       f32x4 (&pv)[NQB]) {
+  // residual codes of row r, and the table entries that seed the
+  // accumulator: rows 4g + v (ids fetched from lanes 4g + v), this lane's
+  // query column of each block
+  auto load_rest = [&](const Tile& t, uint32_t id, ResWords<RB>& rw, f32x4 (&pv)[NQB]) {
+    const bool tok = (t.flags & F_TOK) != 0;
+    const int row = r < t.rows ? r : t.rows - 1;
+    rw.load(tok ? P.residuals + (t.tok0 + row) * ROWB + g * RB : (const uint8_t*)zrow);
+    const uint32_t idc = tok ? (id < max_c ? id : max_c) : max_c + 1;
+    uint32_t idv[4];
 #pragma unroll
-    for (int nb = 0; nb < NQB; ++nb) pv[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    rw.zero();
-    if (t.flags & F_TOK) {
-      const int row = r < t.rows ? r : t.rows - 1;
-      rw.load(P.residuals + (t.tok0 + row) * ROWB + g * RB);
+    for (int v = 0; v < 4; ++v) idv[v] = (uint32_t)__shfl((int)idc, 4 * g + v, 64);
 #pragma unroll
-      for (int nb = 0; nb < NQB; ++nb)
-        if (qlive[nb]) {
+    for (int nb = 0; nb < NQB; ++nb)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) pv[nb][v] = P.table[(int64_t)id[v] * P.n_qtok + qcol[nb]];
-        }
-    }
+      for (int v = 0; v < 4; ++v) pv[nb][v] = P.table[__umul24(idv[v], qmul[nb]) + qbase[nb]];
   };
 
   auto store = [&](int64_t pp, float v) {
@@ -297,49 +322,61 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
     }
   };
 
-  // Software pipeline: ids two tiles ahead, residual codes and table entries
-  // one tile ahead (their addresses need the ids), compute on the current.
-  Tile ta = next_tile();
-  uint32_t ia[4];
-  load_ids(ta, ia);
-  Tile tb = next_tile();
-  uint32_t ib[4];
-  load_ids(tb, ib);
-  ResWords<RB> ra;
-  f32x4 pa[NQB];
-  load_rest(ta, ia, ra, pa);
-  while (ta.flags & F_VALID) {
-    const Tile tc = next_tile();
-    uint32_t ic[4];
-    load_ids(tc, ic);
-    ResWords<RB> rb;
-    f32x4 pb[NQB];
-    load_rest(tb, ib, rb, pb);
-    consume(ta, ra, pa);
-    ta = tb;
-    tb = tc;
-    ra = rb;
+  // Software pipeline over S = PI + PR tile slots: a tile's ids are loaded
+  // S tiles before it is consumed, its residual codes and table entries
+  // (whose addresses need the ids) PR tiles before. Slot indices are
+  // compile-time constants in the unrolled loop, so the ring stays in VGPRs.
+  constexpr int S = PI + PR;
+  Tile tq[S];
+  uint32_t idq[S];
+  ResWords<RB> rq[S];
+  f32x4 pq[S][NQB];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) ib[v] = ic[v];
+  for (int k = 0; k < S; ++k) {
+    tq[k] = next_tile();
+    load_ids(tq[k], idq[k]);
+  }
 #pragma unroll
-    for (int nb = 0; nb < NQB; ++nb) pa[nb] = pb[nb];
+  for (int k = 0; k < PR; ++k) load_rest(tq[k], idq[k], rq[k], pq[k]);
+  // whole rounds of S steps: the tiles after a wave's last one carry no
+  // flags, so their steps compute on zero rows and store nothing
+  while (tq[0].flags & F_VALID) {
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int jr = (j + PR) % S;
+      load_rest(tq[jr], idq[jr], rq[jr], pq[jr]);
+      consume(tq[j], rq[j], pq[j]);
+      tq[j] = next_tile();
+      load_ids(tq[j], idq[j]);
+    }
   }
 }
 
 template <int NKS>
 hipError_t launch_table_t(const ResParams& P, hipStream_t s) {
-  const int64_t waves = (P.n_centroids + 15) / 16;
+  const int64_t waves = (P.n_centroids + 1 + 15) / 16;  // + the zero row
   hipLaunchKernelGGL(centroid_table_kernel<NKS>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0,
                      s, P);
   return hipGetLastError();
 }
 
-template <int NBITS, int NKS, int NQB>
-hipError_t launch_score_t(const ResParams& P, hipStream_t s) {
+template <int NBITS, int NKS, int NQB, int PI, int PR>
+hipError_t launch_score_p(const ResParams& P, hipStream_t s) {
   constexpr int NW = 4;
-  hipLaunchKernelGGL((residual_maxsim_kernel<NBITS, NKS, NQB, NW>),
+  hipLaunchKernelGGL((residual_maxsim_kernel<NBITS, NKS, NQB, NW, PI, PR>),
                      dim3((unsigned)(P.n_q * P.n_chunks)), dim3(NW * 64), 0, s, P);
   return hipGetLastError();
+}
+
+// pipeline depths (ids lead, table/residual lead) of the selectable variants
+template <int NBITS, int NKS, int NQB>
+hipError_t launch_score_t(const ResParams& P, hipStream_t s) {
+  switch (P.pipe) {
+    case 0: return launch_score_p<NBITS, NKS, NQB, 1, 1>(P, s);
+    case 1: return launch_score_p<NBITS, NKS, NQB, 1, 2>(P, s);
+    case 2: return launch_score_p<NBITS, NKS, NQB, 2, 2>(P, s);
+    default: return launch_score_p<NBITS, NKS, NQB, 2, 3>(P, s);
+  }
 }
 
 template <int NBITS, int NKS>
@@ -362,8 +399,32 @@ hipError_t launch_score_dim(const ResParams& P, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_residual(const ResParams& P, hipStream_t s) {
-  hipError_t e = hipSuccess;
+// Device address of this file's zero row, per device (the kernels take it as
+// an argument).
+hipError_t zero_row_address(const char** out) {
+  static std::mutex mu;
+  static std::map<int, const char*> addr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_zero_row));
+    if (e != hipSuccess) return e;
+    it = addr.emplace(dev, (const char*)p).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
+hipError_t launch_residual(const ResParams& Pin, hipStream_t s) {
+  ResParams P = Pin;
+  hipError_t e = zero_row_address(&P.zero_row);
+  if (e != hipSuccess) return e;
+  // without query tokens no table exists and every gather reads the zero row
+  if (P.n_qtok == 0) P.table = (float*)P.zero_row;
   if (P.n_qtok > 0) {
     switch (P.dim) {
       case 64: e = launch_table_t<2>(P, s); break;

@@ -8,6 +8,8 @@ and every query-block count; the full-size case is the benchmark's workload
 (1M documents, 2^17 centroids, 2-bit residuals) checked on sampled documents
 and through the exact top-100.
 """
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -120,11 +122,52 @@ def test_residual_zero_weights_equal_plain_fused_path_on_centroids():
     assert_close_o1(got, _oracle(c), "residual zero weights")
 
 
+@pytest.fixture
+def res_pipe(request, tmp_path):
+    """Forces the residual scorer's load-pipeline variant for every key the
+    test can touch; afterwards restores the packaged tuning."""
+    entries = [{"residual": 1, "nbits": nb, "dim": dm, "nqb": q, "cand": c, "pipe": request.param}
+               for nb in (1, 2, 4) for dm in (64, 128, 256) for q in (1, 2, 4) for c in (0, 1)]
+    path = tmp_path / "res.json"
+    path.write_text(json.dumps({"version": 1, "entries": entries}))
+    M.load_tune_cache(str(path))
+    yield request.param
+    # the packaged cache holds no forced entries for these keys: drop them
+    entries = [dict(e, pipe=2) for e in entries]
+    path.write_text(json.dumps({"version": 1, "entries": entries}))
+    M.load_tune_cache(str(path))
+    M.load_tune_cache(M.default_tune_cache())
+
+
+@pytest.mark.parametrize("res_pipe", [0, 1, 2, 3], indirect=True)
+@pytest.mark.parametrize("nbits", [1, 2, 4])
+def test_residual_every_pipeline_variant(res_pipe, nbits):
+    # ragged docs (tiles of 1..16 rows, empty docs) and candidate lists with
+    # every ring depth
+    c = _case(400, 128, nbits, 300, seed=31 + nbits, nq_lens=[32, 13, 64, 0])
+    cand_off, cand_ids = W.candidates(4, 400, seed=32, size_range=(1, 300))
+    Q, D = _device(c)
+    got = M.residual_score(Q, D).cpu().numpy()
+    assert_close_o1(got, _oracle(c), f"residual pipe {res_pipe}")
+    got_c = M.residual_score(Q, D, M.Candidates(dev(cand_off), dev(cand_ids))).cpu().numpy()
+    assert_close_o1(got_c, _oracle(c, cand_off, cand_ids), f"residual cand pipe {res_pipe}")
+
+
+def test_residual_autotune_keeps_results_within_tolerance(tmp_path):
+    c = _case(3000, 128, 2, 4096, seed=41, nq_lens=[32])
+    Q, D = _device(c)
+    rep = M.residual_autotune(Q, D, reps=2, cache_path=str(tmp_path / "t.json"))
+    assert {t["pipe"] for t in rep["trials"]} == {0, 1, 2, 3}, rep
+    assert '"residual":1' in (tmp_path / "t.json").read_text()
+    assert_close_o1(M.residual_score(Q, D).cpu().numpy(), _oracle(c), "residual after autotune")
+    M.load_tune_cache(M.default_tune_cache())
+
+
 def test_residual_no_documents_and_workspace_checks():
     c = _case(50, 128, 2, 64, seed=5, nq_lens=[32])
     Q, D = _device(c)
     need = M.residual_workspace_bytes(Q, D)
-    assert need >= 64 * 32 * 4 and need % 256 == 0
+    assert need >= 65 * 32 * 4 and need % 256 == 0
     ws = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
     with pytest.raises(M.MaxSimError) as e:
         M.residual_score(Q, D, workspace=ws)
