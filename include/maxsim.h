@@ -212,19 +212,20 @@ maxsim_status maxsim_pq_score(const maxsim_csr* queries, const maxsim_pq_docs* d
 
 /*
  * MaxSim over residual-compressed documents: Eq. (1) on the decoded tokens,
- * computed as q_i . x_j = q_i . C[id_j] + q_i . r_j. The first call builds
+ * computed as q_i . x_j = q_i . C[id_j] + q_i . r_j. The call first builds
  * the table P[c, i] = C[c] . q_i (FP32, every centroid against every query
  * token of the batch) in `workspace`; the fused scorer then reads each
  * token's id and packed residual once, gathers P[id_j, i], decodes the
  * residual in registers and adds q_i . r_j before the max over tokens and the
  * sum over query tokens. Decoded vectors are never written.
- *   queries    F16, same dim, max_len <= 64. n_centroids and
- *              queries->n_tokens below 2^24 and (n_centroids + 1) *
- *              queries->n_tokens below 2^32 (else MAXSIM_EUNSUPPORTED).
+ *   queries    F16, same dim, max_len <= 64. Each query owns
+ *              W = 16 * nqb table columns, nqb = ceil(max_len / 16) rounded
+ *              up to a power of two; n_centroids and n_queries * W must stay
+ *              below 2^24 and their product below 2^32 (else
+ *              MAXSIM_EUNSUPPORTED).
  *   cand       as for maxsim_score.
- *   workspace  maxsim_residual_score_workspace_size() bytes: the table plus
- *              one row of zeros, (n_centroids + 1) * queries->n_tokens * 4,
- *              rounded up to 256.
+ *   workspace  maxsim_residual_score_workspace_size() bytes:
+ *              n_centroids * n_queries * W * 4, rounded up to 256.
  */
 size_t maxsim_residual_score_workspace_size(const maxsim_csr* queries,
                                             const maxsim_residual_docs* docs,

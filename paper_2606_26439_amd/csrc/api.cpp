@@ -747,12 +747,13 @@ maxsim_status plan_residual(const maxsim_csr* q, const maxsim_residual_docs* d,
   if (span_bound >= 0x7fffffffLL - 64)
     return fail(MAXSIM_EUNSUPPORTED, "residual: too many documents per work item");
   P.n_chunks = (int)n_chunks;
-  if (d->n_centroids >= (1 << 24) || q->n_tokens >= (1 << 24) ||
-      (uint64_t)(d->n_centroids + 1) * (uint64_t)q->n_tokens >= (1ull << 32))
+  P.n_cols = q->n_sets * 16 * P.nqb;
+  if (d->n_centroids >= (1 << 24) || P.n_cols >= (1 << 24) ||
+      (uint64_t)d->n_centroids * (uint64_t)P.n_cols >= (1ull << 32))
     return fail(MAXSIM_EUNSUPPORTED,
-                "residual: n_centroids and query tokens below 2^24, and (n_centroids + 1) x "
-                "query tokens below 2^32 table entries");
-  const size_t table = (size_t)(d->n_centroids + 1) * (size_t)q->n_tokens * 4;
+                "residual: n_centroids and n_queries x 16 x ceil(max_len / 16) (rounded up to a "
+                "power of two) below 2^24, their product below 2^32 table entries");
+  const size_t table = (size_t)d->n_centroids * (size_t)P.n_cols * 4;
   pl.ws = (table + 255) / 256 * 256;
   int pipe = force_pipe;
   if (pipe < 0) {

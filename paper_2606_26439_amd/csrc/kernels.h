@@ -93,7 +93,7 @@ struct ResParams {
   const void* q_tok;  // F16 [n_qtok, dim]
   const int64_t* q_off;
   int64_t n_q;
-  int64_t n_qtok;         // q_off[n_q] (host copy): row length of `table`
+  int64_t n_qtok;         // q_off[n_q] (host copy)
   const void* centroids;  // F16 [n_centroids, dim]
   int64_t n_centroids;
   const void* weights;  // F16 [2^nbits]
@@ -104,8 +104,9 @@ struct ResParams {
   const int64_t* cand_off;
   const int32_t* cand_ids;
   float* scores;
-  float* table;  // workspace: [n_centroids + 1, n_qtok] FP32 (last row zeros)
+  float* table;  // workspace: [n_centroids, n_cols] FP32
   const char* zero_row;  // set by launch_residual: 1 KiB of device zeros
+  int64_t n_cols;        // n_q * 16 * nqb: each query owns 16 * nqb columns
   int32_t dim;    // 64, 128 or 256
   int32_t nbits;  // 1, 2 or 4
   int32_t nqb;    // 16-column query blocks (1, 2, 4)

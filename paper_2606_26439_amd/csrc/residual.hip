@@ -6,20 +6,26 @@
 // score is Eq. (1) on these vectors, computed through the split
 //   q_i . x_j = q_i . C[id_j] + q_i . r_j.
 // The first term does not depend on the document, so one small MFMA kernel
-// tabulates P[c, i] = C[c] . q_i for every centroid c and query token i (FP32,
-// in the caller's workspace). The fused kernel then reads each document
-// token's id (4 B) and packed residual (dim * NBITS / 8 B) once from HBM,
-// seeds the accumulator of a 16-token tile with the gathered P entries,
-// decodes the residual codes into FP16 through a byte-indexed table in LDS,
-// and adds q_i . r_j with v_mfma_f32_16x16x32_f16 before the running max over
-// tokens and the sum over query tokens. Decoded vectors are never written.
+// tabulates P[c, (a, t)] = C[c] . q_t of query a for every centroid c (FP32,
+// in the caller's workspace; each query owns QW = 16 * ceil(max_len / 16)
+// columns, zero past its last token). The fused kernel then reads each
+// document token's id (4 B) and packed residual (dim * NBITS / 8 B) once from
+// HBM, decodes the residual codes into FP16 through a byte-indexed table in
+// LDS, and computes q_t . r_j with v_mfma_f32_16x16x32_f16 whose accumulator
+// starts from the gathered table entries; the running max over tokens and the
+// sum over query tokens follow. Decoded vectors are never written.
 //
-// Column order. Lane (r, g) of a k-step holds 8 consecutive columns of its
-// row; here lane group g owns the contiguous quarter [g * dim/4, (g+1) * dim/4)
-// of the dimensions and k-step s takes columns g * dim/4 + 8 s .. + 7. The
-// query operand uses the same order, so every product pairs equal columns,
-// and a lane's residual codes for all k-steps are one contiguous
-// dim * NBITS / 32-byte piece of the packed row.
+// Operand layout. The MFMA's rows are query tokens and its columns document
+// tokens, so lane (r, g) of the accumulator holds document row r of the tile
+// against query tokens 4g .. 4g+3 of each 16-row query block: the table
+// entries it needs are consecutive in the centroid's table row and arrive in
+// 16-byte loads. Query block nb's MFMA row 4g + v is query token
+// 4 NQB g + 4 nb + v, so a lane's entries for all blocks are the 4 NQB
+// consecutive columns starting at 4 NQB g. In the k dimension lane group g
+// owns the contiguous quarter [g * dim/4, (g+1) * dim/4) of the dimensions
+// and k-step s takes columns g * dim/4 + 8 s .. + 7 of both operands, so a
+// lane's residual codes for all k-steps are one contiguous dim * NBITS / 32-byte
+// piece of the packed row.
 #include <map>
 #include <mutex>
 
@@ -28,8 +34,9 @@
 
 namespace {
 
-// P[c, j] = C[c] . q_j over all centroids c and all query tokens j of the
-// batch (row length n_qtok). One wave per 16 centroids; 4 waves per group.
+// P[c, a * QW + t] = C[c] . q_t of query a (t < its length), 0 for t up to
+// QW. One wave per 16 centroids and every 16-column block of every query;
+// 4 waves per group.
 template <int NKS>
 __global__ __launch_bounds__(256) void centroid_table_kernel(ResParams P) {
   constexpr int DIM = NKS * 32;
@@ -37,17 +44,20 @@ __global__ __launch_bounds__(256) void centroid_table_kernel(ResParams P) {
   const int r = lane & 15, g = lane >> 4;
   const int64_t c0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
   const int64_t n_c = P.n_centroids;
-  if (c0 > n_c) return;  // uniform per wave
+  if (c0 >= n_c) return;  // uniform per wave
   const int64_t cr = c0 + r < n_c ? c0 + r : n_c - 1;
   const _Float16* crow = (const _Float16*)P.centroids + cr * DIM + g * (DIM / 4);
   f16x8 a[NKS];
 #pragma unroll
   for (int s = 0; s < NKS; ++s) a[s] = *(const f16x8*)(crow + 8 * s);
-  const int64_t nqt = P.n_qtok;
-  for (int64_t j0 = 0; j0 < nqt; j0 += 16) {
-    const int64_t j = j0 + r;
-    const bool live = j < nqt;
-    const _Float16* qrow = (const _Float16*)P.q_tok + (live ? j : 0) * DIM + g * (DIM / 4);
+  const int64_t ncols = P.n_cols;
+  const int bpq = P.nqb;
+  for (int64_t blk = 0; blk < P.n_q * bpq; ++blk) {
+    const int64_t qa = blk / bpq;
+    const int t = (int)(blk % bpq) * 16 + r;
+    const int64_t q0 = sload_i64(P.q_off, qa);
+    const bool live = t < (int)(sload_i64(P.q_off, qa + 1) - q0);
+    const _Float16* qrow = (const _Float16*)P.q_tok + (live ? q0 + t : 0) * DIM + g * (DIM / 4);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
@@ -56,12 +66,11 @@ __global__ __launch_bounds__(256) void centroid_table_kernel(ResParams P) {
       acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[s], __builtin_bit_cast(f16x8, v), acc, 0, 0,
                                                    0);
     }
-    // lane holds centroids c0 + 4g + v, query token j; row n_c is all zeros
-    // (the entry that lanes without a live query column read)
+    // lane holds centroids c0 + 4g + v, column blk * 16 + r
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t c = c0 + 4 * g + v;
-      if (live && c <= n_c) P.table[c * nqt + j] = c < n_c ? acc[v] : 0.f;
+      if (c < n_c) P.table[c * ncols + blk * 16 + r] = acc[v];
     }
   }
 }
@@ -139,25 +148,21 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
     lut[e] = ((const _Float16*)P.weights)[(b >> (f * NBITS)) & ((1 << NBITS) - 1)];
   }
 
-  // query operand: block nb holds tokens nb*16 + r of query a (zero past its end)
+  // query operand (the MFMA's rows): block nb, row r is query token
+  // 4 NQB (r / 4) + 4 nb + r % 4 of query a, zero past its end
   const int64_t qa0 = uniform64(sload_i64(P.q_off, a));
   const int nq = uniform((int)(sload_i64(P.q_off, a + 1) - qa0));
-  f16x8 qb[NQB][NKS];
-  int64_t qcol[NQB];  // table column of this lane's query token per block
-  uint32_t qcol32[NQB];
-  bool qlive[NQB];
+  f16x8 qa[NQB][NKS];
 #pragma unroll
   for (int nb = 0; nb < NQB; ++nb) {
-    const int t = nb * 16 + r;
-    qlive[nb] = t < nq;
-    qcol[nb] = qa0 + (qlive[nb] ? t : 0);
-    qcol32[nb] = (uint32_t)qcol[nb];
-    const _Float16* qrow = (const _Float16*)P.q_tok + qcol[nb] * DIM + g * (DIM / 4);
+    const int t = 4 * NQB * (r >> 2) + 4 * nb + (r & 3);
+    const bool live = t < nq;
+    const _Float16* qrow = (const _Float16*)P.q_tok + (qa0 + (live ? t : 0)) * DIM + g * (DIM / 4);
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
       u32x4 v = {0u, 0u, 0u, 0u};
-      if (qlive[nb]) v = *(const u32x4*)(qrow + 8 * s);
-      qb[nb][s] = __builtin_bit_cast(f16x8, v);
+      if (live) v = *(const u32x4*)(qrow + 8 * s);
+      qa[nb][s] = __builtin_bit_cast(f16x8, v);
     }
   }
   const bool poison = nq > NQB * 16;
@@ -217,48 +222,34 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
     return t;
   };
 
-  const uint32_t max_c = (uint32_t)(P.n_centroids - 1);
-  // The host keeps n_centroids + 1 and n_qtok below 2^24 and the table below
-  // 2^32 entries, so table indices are 24 x 24-bit products in 32 bits.
-  // Table row n_centroids is all zeros: a lane whose query column is not live
-  // reads it (multiplier 0, base the zero row's first entry), and so does
-  // every lane of a tile without tokens (id n_centroids).
-  const uint32_t nqt = (uint32_t)P.n_qtok;
-  const uint32_t zero_idx = (uint32_t)P.n_centroids * nqt;
-  uint32_t qmul[NQB], qbase[NQB];
-#pragma unroll
-  for (int nb = 0; nb < NQB; ++nb) {
-    qmul[nb] = qlive[nb] ? nqt : 0u;
-    qbase[nb] = qlive[nb] ? qcol32[nb] : zero_idx;
-  }
-  const char* zrow = P.zero_row;
   // Every tile issues the same loads (a tile without tokens reads the zero
-  // row instead), so the count of loads in flight is the same on every path
-  // and the compiler's waits stay exact across the ring. The document
-  // streams are read once: non-temporal loads keep them from displacing the
-  // centroid table in the caches.
-  // Centroid id of tile row r (clamped to the tile's rows; clamped to the
-  // table where it is used, so a bad id cannot read outside it).
+  // row, and table row 0, instead), so the count of loads in flight is the
+  // same on every path and the compiler's waits stay exact across the ring.
+  // The document streams are read once: non-temporal loads keep them from
+  // displacing the centroid table in the caches. The host keeps n_centroids
+  // and the table's row length below 2^24 and the table below 2^32 entries,
+  // so table indices are 24 x 24-bit products in 32 bits.
+  const uint32_t max_c = (uint32_t)(P.n_centroids - 1);
+  const uint32_t ncols = (uint32_t)P.n_cols;
+  const uint32_t col0 = (uint32_t)a * (uint32_t)(16 * NQB) + 4 * NQB * g;
+  const char* zrow = P.zero_row;
+  // centroid id of tile row r (clamped to the tile's rows; clamped to the
+  // table where it is used, so a bad id cannot read outside it)
   auto load_ids = [&](const Tile& t, uint32_t& id) {
     const int row = r < t.rows ? r : t.rows - 1;
     const int32_t* src = (t.flags & F_TOK) ? P.ids + t.tok0 + row : (const int32_t*)zrow;
     id = (uint32_t)__builtin_nontemporal_load(src);
   };
   // residual codes of row r, and the table entries that seed the
-  // accumulator: rows 4g + v (ids fetched from lanes 4g + v), this lane's
-  // query column of each block
+  // accumulator: this row's centroid, query tokens 4 NQB g .. + 4 NQB - 1
   auto load_rest = [&](const Tile& t, uint32_t id, ResWords<RB>& rw, f32x4 (&pv)[NQB]) {
-    const bool tok = (t.flags & F_TOK) != 0;
     const int row = r < t.rows ? r : t.rows - 1;
-    rw.load(tok ? P.residuals + (t.tok0 + row) * ROWB + g * RB : (const uint8_t*)zrow);
-    const uint32_t idc = tok ? (id < max_c ? id : max_c) : max_c + 1;
-    uint32_t idv[4];
+    rw.load((t.flags & F_TOK) ? P.residuals + (t.tok0 + row) * ROWB + g * RB
+                              : (const uint8_t*)zrow);
+    const uint32_t idc = id < max_c ? id : max_c;
+    const f32x4* src = (const f32x4*)(P.table + (__umul24(idc, ncols) + col0));
 #pragma unroll
-    for (int v = 0; v < 4; ++v) idv[v] = (uint32_t)__shfl((int)idc, 4 * g + v, 64);
-#pragma unroll
-    for (int nb = 0; nb < NQB; ++nb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) pv[nb][v] = P.table[__umul24(idv[v], qmul[nb]) + qbase[nb]];
+    for (int nb = 0; nb < NQB; ++nb) pv[nb] = src[nb];
   };
 
   auto store = [&](int64_t pp, float v) {
@@ -266,10 +257,26 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
     P.scores[has_cand ? pp : a * P.n_docs + pp] = v;
   };
 
-  float mx[NQB];
+  // running max per (query block, accumulator row) over this lane's document
+  // rows; reduced over the 16 rows of the tile at the document's end
+  f32x4 mx[NQB];
 #pragma unroll
-  for (int nb = 0; nb < NQB; ++nb) mx[nb] = -__builtin_inff();
+  for (int nb = 0; nb < NQB; ++nb) mx[nb] = f32x4{-__builtin_inff(), -__builtin_inff(),
+                                                  -__builtin_inff(), -__builtin_inff()};
   const char* lutb = (const char*)lut;
+
+  // max over the 16 lanes of a row group (rotations by 8, 4, 2, 1)
+  auto row_max = [](float v) {
+    v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                               0, __builtin_bit_cast(int, v), 0x128, 0xF, 0xF, false)));
+    v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                               0, __builtin_bit_cast(int, v), 0x124, 0xF, 0xF, false)));
+    v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                               0, __builtin_bit_cast(int, v), 0x122, 0xF, 0xF, false)));
+    v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                               0, __builtin_bit_cast(int, v), 0x121, 0xF, 0xF, false)));
+    return v;
+  };
 
   auto consume = [&](const Tile& t, const ResWords<RB>& rw, const f32x4 (&pv)[NQB]) {
     if (t.flags & F_EMPTY) {
@@ -283,41 +290,40 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
     for (int s = 0; s < NKS; ++s) {
       // bytes s*NBITS .. s*NBITS + NBITS - 1 of the lane's piece decode to
       // the 8 residual values of k-step s
-      u32x4 av;
+      u32x4 bv;
       if constexpr (NBITS == 1) {
-        av = *(const u32x4*)(lutb + rw.byte_offset(s, EB_LOG2));
+        bv = *(const u32x4*)(lutb + rw.byte_offset(s, EB_LOG2));
       } else if constexpr (NBITS == 2) {
         const uint2 lo = *(const uint2*)(lutb + rw.byte_offset(2 * s, EB_LOG2));
         const uint2 hi = *(const uint2*)(lutb + rw.byte_offset(2 * s + 1, EB_LOG2));
-        av = u32x4{lo.x, lo.y, hi.x, hi.y};
+        bv = u32x4{lo.x, lo.y, hi.x, hi.y};
       } else {
-        av = u32x4{*(const uint32_t*)(lutb + rw.byte_offset(4 * s, EB_LOG2)),
+        bv = u32x4{*(const uint32_t*)(lutb + rw.byte_offset(4 * s, EB_LOG2)),
                    *(const uint32_t*)(lutb + rw.byte_offset(4 * s + 1, EB_LOG2)),
                    *(const uint32_t*)(lutb + rw.byte_offset(4 * s + 2, EB_LOG2)),
                    *(const uint32_t*)(lutb + rw.byte_offset(4 * s + 3, EB_LOG2))};
       }
-      const f16x8 ah = __builtin_bit_cast(f16x8, av);
+      const f16x8 bh = __builtin_bit_cast(f16x8, bv);
 #pragma unroll
       for (int nb = 0; nb < NQB; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, qb[nb][s], acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(qa[nb][s], bh, acc[nb], 0, 0, 0);
     }
 #pragma unroll
     for (int nb = 0; nb < NQB; ++nb)
-      mx[nb] = fmaxf(mx[nb], fmaxf(fmaxf(acc[nb].x, acc[nb].y), fmaxf(acc[nb].z, acc[nb].w)));
+#pragma unroll
+      for (int v = 0; v < 4; ++v) mx[nb][v] = fmaxf(mx[nb][v], acc[nb][v]);
     if (t.flags & F_DLAST) {
+      // max over the document's rows (lanes r), then the sum over query
+      // tokens: in-lane over blocks and rows 4g + v, then across g
       float qsum = 0.f;
 #pragma unroll
       for (int nb = 0; nb < NQB; ++nb) {
-        float v = mx[nb];
-        v = fmaxf(v, xor_shfl(v, 16));
-        v = fmaxf(v, xor_shfl(v, 32));
-        qsum += v;
-        mx[nb] = -__builtin_inff();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) qsum += row_max(mx[nb][v]);
+        mx[nb] = f32x4{-__builtin_inff(), -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
       }
-      qsum += xor_shfl(qsum, 8);
-      qsum += xor_shfl(qsum, 4);
-      qsum += xor_shfl(qsum, 2);
-      qsum += xor_shfl(qsum, 1);
+      qsum += xor_shfl(qsum, 16);
+      qsum += xor_shfl(qsum, 32);
       if (lane == 0) store(t.pp, qsum);
     }
   };
@@ -354,7 +360,7 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
 
 template <int NKS>
 hipError_t launch_table_t(const ResParams& P, hipStream_t s) {
-  const int64_t waves = (P.n_centroids + 1 + 15) / 16;  // + the zero row
+  const int64_t waves = (P.n_centroids + 15) / 16;
   hipLaunchKernelGGL(centroid_table_kernel<NKS>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0,
                      s, P);
   return hipGetLastError();
@@ -423,9 +429,7 @@ hipError_t launch_residual(const ResParams& Pin, hipStream_t s) {
   ResParams P = Pin;
   hipError_t e = zero_row_address(&P.zero_row);
   if (e != hipSuccess) return e;
-  // without query tokens no table exists and every gather reads the zero row
-  if (P.n_qtok == 0) P.table = (float*)P.zero_row;
-  if (P.n_qtok > 0) {
+  {
     switch (P.dim) {
       case 64: e = launch_table_t<2>(P, s); break;
       case 128: e = launch_table_t<4>(P, s); break;

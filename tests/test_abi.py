@@ -130,7 +130,8 @@ def test_residual_workspace_is_the_centroid_table():
     qc = _csr(n_tokens=37, max_len=37)
     rc = _res(n_c=1001)
     need = L.maxsim_residual_score_workspace_size(ctypes.byref(qc), ctypes.byref(rc), None)
-    assert need == (1002 * 37 * 4 + 255) // 256 * 256  # the table and a zero row
+    # one query of max_len 37: 64 columns (16 x ceil(37 / 16) rounded up to 4 blocks)
+    assert need == (1001 * 64 * 4 + 255) // 256 * 256
     assert L.maxsim_residual_score(ctypes.byref(qc), ctypes.byref(rc), None, ctypes.c_void_p(16),
                                    ctypes.c_void_p(256), need - 1, None) == 3
     assert L.maxsim_validate_residual(None, ctypes.byref(rc), None, None, None) == 1
