@@ -552,7 +552,8 @@ def bench_residual(n_docs=1_000_000, nq=32, dim=128, n_centroids=1 << 17, nbits_
 
 def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_000, k=100,
                   n_sets=2048, n_sat=1500):
-    """5M-doc FP16 pool + PQ copy; top-100. Per mode, the saturation rate is
+    """5M-doc FP16 pool + PQ copy + residual-compressed copy (2^18 centroids,
+    2-bit codes); top-100. Per mode, the saturation rate is
     measured first (every request queued at once), then open-loop Poisson
     arrivals run at fixed fractions of it, n_req requests per level. Requests
     cycle through n_sets seeded (query, candidate set) pairs."""
@@ -580,8 +581,16 @@ def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_0
     codes = W.pq_codes_gpu(T, 8, 256, seed=2)
     cb_np = W.pq_codebooks(8, 256, 16, seed=2)
     pq = M.PQDocs(torch.from_numpy(cb_np).cuda(), codes, d_off)
+    n_cen = 1 << 18
+    cen_np = W.residual_centroids(n_cen, 128, seed=5)
+    w_np = W.residual_weights(2)
+    rids = W.residual_ids_gpu(T, n_cen, seed=6)
+    rcodes = W.residual_codes_gpu(T, 128, 2, seed=6)
+    res = M.ResidualDocs(torch.from_numpy(cen_np).cuda(), torch.from_numpy(w_np).cuda(), rids,
+                         rcodes, d_off, 2)
     log(f"[bench] serving pool: {n_pool} docs, {T} tokens, "
-        f"{tok.numel() * 2 / 1e9:.1f} GB FP16 + {codes.numel() / 1e9:.2f} GB codes, "
+        f"{tok.numel() * 2 / 1e9:.1f} GB FP16 + {codes.numel() / 1e9:.2f} GB PQ codes + "
+        f"{(rids.numel() * 4 + rcodes.numel()) / 1e9:.2f} GB residual, "
         f"built in {time.time() - t0:.1f}s")
     counter = [0]
 
@@ -591,10 +600,11 @@ def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_0
         j = i % n_sets
         return S.Request(i, queries[j], c_ids[c_off[j]:c_off[j + 1]], mode=mode)
 
-    backend = S.GpuBackend(pool, pq, k=k, n_slots=3)
-    # warm-up: grow every slot's buffers to a large batch and touch both modes
+    backend = S.GpuBackend(pool, pq, k=k, n_slots=3, pool_res=res)
+    modes = ("exact", "pq", "residual")
+    # warm-up: grow every slot's buffers to a large batch and touch every mode
     S.Server(S.Scheduler(128, k, max_inflight=3), backend).run(
-        [mk("exact" if j % 2 else "pq") for j in range(16)])
+        [mk(modes[j % 3]) for j in range(24)])
     import gc
     gc.collect()
     gc.disable()  # no collector pauses inside the timed runs
@@ -611,7 +621,7 @@ def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_0
         return srv, done, wall
 
     results, saturation = [], {}
-    for mode in ("exact", "pq"):
+    for mode in modes:
         reqs = [mk(mode) for _ in range(n_sat)]
         srv, done, wall = run(reqs, np.zeros(n_sat))
         sat = len(done) / wall
@@ -643,7 +653,7 @@ def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_0
     # (a swap is allowed only between near-ties)
     row_of = {int(r): i for i, r in enumerate(check_rows)}
     worst, id_ok, n_checked = 0.0, True, 0
-    for mode in ("exact", "pq"):
+    for mode in modes:
         reqs = [S.Request(10 ** 9 + j, queries[j], c_ids[c_off[j]:c_off[j + 1]], mode=mode)
                 for j in check_sets]
         S.Server(S.Scheduler(128, k), backend).run(reqs)
@@ -658,6 +668,11 @@ def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_0
             if mode == "pq":
                 cc = codes[torch.from_numpy(rows).cuda()].cpu().numpy()
                 want = oracle.pq_decode_score(qv, [0, nq], cc, cb_np.astype(np.float64), s_off)
+            elif mode == "residual":
+                rt = torch.from_numpy(rows).cuda()
+                want = oracle.residual_decode_score(
+                    qv, [0, nq], rids[rt].cpu().numpy(), rcodes[rt].cpu().numpy(),
+                    cen_np.astype(np.float64), w_np.astype(np.float64), 2, s_off)
             else:
                 dv, _ = oracle.exact_values(check_f32[[row_of[int(x)] for x in rows]], "f16")
                 want = oracle.maxsim(qv, [0, nq], dv, s_off)
@@ -673,9 +688,10 @@ def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_0
             n_checked += 1
     log(f"[bench] serving: {n_checked} served requests vs oracle: max rel err {worst:.1e}, "
         f"top-{k} ids agree {id_ok}")
-    del tok, codes, pool, pq
+    del tok, codes, pool, pq, rids, rcodes, res
     torch.cuda.empty_cache()
-    return {"pool_docs": n_pool, "pool_tokens": T, "k": k, "saturation": saturation,
+    return {"pool_docs": n_pool, "pool_tokens": T, "k": k, "residual_centroids": n_cen,
+            "saturation": saturation,
             "levels": results,
             "sampled_requests_vs_oracle": {"n": n_checked, "max_rel_err": worst,
                                            "topk_ids_agree_up_to_near_ties": id_ok,

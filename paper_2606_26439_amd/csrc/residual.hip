@@ -17,11 +17,12 @@
 //
 // Operand layout. The MFMA's rows are query tokens and its columns document
 // tokens, so lane (r, g) of the accumulator holds document row r of the tile
-// against query tokens 4g .. 4g+3 of each 16-row query block: the table
-// entries it needs are consecutive in the centroid's table row and arrive in
-// 16-byte loads. Query block nb's MFMA row 4g + v is query token
-// 4 NQB g + 4 nb + v, so a lane's entries for all blocks are the 4 NQB
-// consecutive columns starting at 4 NQB g. In the k dimension lane group g
+// against query tokens 16 nb + 4g .. 16 nb + 4g + 3 of query block nb: the
+// table entries it needs are consecutive in the centroid's table row and
+// arrive in one 16-byte load per block. The sum over query tokens runs per
+// row position over the blocks in order, then over the positions in a fixed
+// tree, so a query scores the same bits whatever block count its batch uses
+// (extra blocks add exact zeros at the end). In the k dimension lane group g
 // owns the contiguous quarter [g * dim/4, (g+1) * dim/4) of the dimensions
 // and k-step s takes columns g * dim/4 + 8 s .. + 7 of both operands, so a
 // lane's residual codes for all k-steps are one contiguous dim * NBITS / 32-byte
@@ -149,13 +150,13 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
   }
 
   // query operand (the MFMA's rows): block nb, row r is query token
-  // 4 NQB (r / 4) + 4 nb + r % 4 of query a, zero past its end
+  // 16 nb + r of query a, zero past its end
   const int64_t qa0 = uniform64(sload_i64(P.q_off, a));
   const int nq = uniform((int)(sload_i64(P.q_off, a + 1) - qa0));
   f16x8 qa[NQB][NKS];
 #pragma unroll
   for (int nb = 0; nb < NQB; ++nb) {
-    const int t = 4 * NQB * (r >> 2) + 4 * nb + (r & 3);
+    const int t = 16 * nb + r;
     const bool live = t < nq;
     const _Float16* qrow = (const _Float16*)P.q_tok + (qa0 + (live ? t : 0)) * DIM + g * (DIM / 4);
 #pragma unroll
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
   // so table indices are 24 x 24-bit products in 32 bits.
   const uint32_t max_c = (uint32_t)(P.n_centroids - 1);
   const uint32_t ncols = (uint32_t)P.n_cols;
-  const uint32_t col0 = (uint32_t)a * (uint32_t)(16 * NQB) + 4 * NQB * g;
+  const uint32_t col0 = (uint32_t)a * (uint32_t)(16 * NQB) + 4 * g;
   const char* zrow = P.zero_row;
   // centroid id of tile row r (clamped to the tile's rows; clamped to the
   // table where it is used, so a bad id cannot read outside it)
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
     id = (uint32_t)__builtin_nontemporal_load(src);
   };
   // residual codes of row r, and the table entries that seed the
-  // accumulator: this row's centroid, query tokens 4 NQB g .. + 4 NQB - 1
+  // accumulator: this row's centroid, query tokens 16 nb + 4g .. + 3
   auto load_rest = [&](const Tile& t, uint32_t id, ResWords<RB>& rw, f32x4 (&pv)[NQB]) {
     const int row = r < t.rows ? r : t.rows - 1;
     rw.load((t.flags & F_TOK) ? P.residuals + (t.tok0 + row) * ROWB + g * RB
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
     const uint32_t idc = id < max_c ? id : max_c;
     const f32x4* src = (const f32x4*)(P.table + (__umul24(idc, ncols) + col0));
 #pragma unroll
-    for (int nb = 0; nb < NQB; ++nb) pv[nb] = src[nb];
+    for (int nb = 0; nb < NQB; ++nb) pv[nb] = src[4 * nb];
   };
 
   auto store = [&](int64_t pp, float v) {
@@ -314,14 +315,16 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
       for (int v = 0; v < 4; ++v) mx[nb][v] = fmaxf(mx[nb][v], acc[nb][v]);
     if (t.flags & F_DLAST) {
       // max over the document's rows (lanes r), then the sum over query
-      // tokens: in-lane over blocks and rows 4g + v, then across g
-      float qsum = 0.f;
+      // tokens: per row position 4g + v over the blocks in order, then over
+      // v and g in a fixed tree
+      float sv[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int nb = 0; nb < NQB; ++nb) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) qsum += row_max(mx[nb][v]);
+        for (int v = 0; v < 4; ++v) sv[v] += row_max(mx[nb][v]);
         mx[nb] = f32x4{-__builtin_inff(), -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
       }
+      float qsum = (sv[0] + sv[1]) + (sv[2] + sv[3]);
       qsum += xor_shfl(qsum, 16);
       qsum += xor_shfl(qsum, 32);
       if (lane == 0) store(t.pp, qsum);

@@ -29,7 +29,8 @@ class Request:
     query: np.ndarray          # [Nq, d] float32 (converted on the device)
     cand_ids: np.ndarray       # [n_cand] int32 ids into the pool
     arrival: float = 0.0       # clock time of arrival
-    mode: str = "exact"        # "exact" (fused MaxSim) or "pq" (fused PQ)
+    mode: str = "exact"        # "exact" (fused MaxSim), "pq" (fused PQ) or
+                               # "residual" (residual-compressed documents)
     deadline: Optional[float] = None
     # filled on completion
     status: str = "pending"    # pending | queued | running | done | timeout | cancelled | error | rejected
@@ -171,11 +172,12 @@ class GpuBackend(Backend):
     top-k rows."""
 
     def __init__(self, pool_docs, pool_pq=None, k: int = 100, n_slots: int = 3,
-                 device: str = "cuda"):
+                 device: str = "cuda", pool_res=None):
         import torch
         from . import _binding as B
         self.torch, self.B = torch, B
         self.docs, self.pq, self.k, self.device = pool_docs, pool_pq, k, device
+        self.res = pool_res
         self.slots = [dict(stream=torch.cuda.Stream(device=device), busy=False, cap=0)
                       for _ in range(n_slots)]
 
@@ -234,6 +236,10 @@ class GpuBackend(Backend):
                 qt, _ = B.quantize(q32, "f16", stream=s)
                 Q = B.Tokens(qt, qoff, "f16", None, max_len=int(nq.max()))
                 scores = B.pq_score(Q, self.pq, cand, stream=s)
+            elif batch.mode == "residual":
+                qt, _ = B.quantize(q32, "f16", stream=s)
+                Q = B.Tokens(qt, qoff, "f16", None, max_len=int(nq.max()))
+                scores = B.residual_score(Q, self.res, cand, stream=s)
             else:
                 qt, qs = B.quantize(q32, self.docs.dtype, stream=s)
                 Q = B.Tokens(qt, qoff, self.docs.dtype, qs, max_len=int(nq.max()))

@@ -1,6 +1,6 @@
 """Serving on the GPU: every request's top-k is the same alone and in a mix
-of concurrently batched requests (bit for bit), for exact and PQ scoring,
-and agrees with the FP64 oracle's ranking."""
+of concurrently batched requests (bit for bit), for exact, PQ and
+residual-compressed scoring, and agrees with the FP64 oracle's ranking."""
 import numpy as np
 import pytest
 import torch
@@ -25,7 +25,14 @@ def pool():
     cb = W.pq_codebooks(8, 256, 16, seed=2)
     codes = W.pq_codes(int(c["d_off"][-1]), seed=2)
     pq = M.PQDocs(dev(cb), dev(codes), d_off)
-    return dict(docs=docs, pq=pq, d=c["d"], d_off=c["d_off"], cb=cb, codes=codes)
+    T = int(c["d_off"][-1])
+    cen = W.residual_centroids(512, 128, seed=5)
+    wts = W.residual_weights(2)
+    rids = W.residual_ids(T, 512, seed=6)
+    rcodes = W.residual_codes(T, 128, 2, seed=6)
+    res = M.ResidualDocs(dev(cen), dev(wts), dev(rids), dev(rcodes), d_off, 2)
+    return dict(docs=docs, pq=pq, res=res, d=c["d"], d_off=c["d_off"], cb=cb, codes=codes,
+                cen=cen, wts=wts, rids=rids, rcodes=rcodes)
 
 
 def _requests(n, seed=0):
@@ -35,7 +42,7 @@ def _requests(n, seed=0):
     for i in range(n):
         q = W.unit_tokens(int(g.integers(8, 65)), 128, g)
         reqs.append(S.Request(i, q, ids[off[i]:off[i + 1]].copy(),
-                              mode="pq" if i % 3 == 2 else "exact"))
+                              mode=("exact", "pq", "residual")[(i // 4) % 3]))
     return reqs
 
 
@@ -45,7 +52,7 @@ def _clone(r):
 
 def test_alone_equals_mixed(pool):
     reqs = _requests(60)
-    be = S.GpuBackend(pool["docs"], pool["pq"], k=100, n_slots=3)
+    be = S.GpuBackend(pool["docs"], pool["pq"], k=100, n_slots=3, pool_res=pool["res"])
     mixed = [_clone(r) for r in reqs]
     t0 = 0.0
     arr = W.poisson_arrivals(len(mixed), 20000.0, seed=9)
@@ -67,7 +74,7 @@ def test_alone_equals_mixed(pool):
 
 def test_served_topk_matches_oracle(pool):
     reqs = _requests(6, seed=5)
-    be = S.GpuBackend(pool["docs"], pool["pq"], k=100)
+    be = S.GpuBackend(pool["docs"], pool["pq"], k=100, pool_res=pool["res"])
     S.Server(S.Scheduler(128, 100), be).run(reqs)
     dv, _ = oracle.exact_values(pool["d"], "f16")
     for r in reqs:
@@ -76,6 +83,11 @@ def test_served_topk_matches_oracle(pool):
         if r.mode == "pq":
             want = oracle.pq_decode_score(qv, [0, nq], pool["codes"], pool["cb"].astype(np.float64),
                                           pool["d_off"], [0, len(r.cand_ids)], r.cand_ids)
+        elif r.mode == "residual":
+            want = oracle.residual_decode_score(qv, [0, nq], pool["rids"], pool["rcodes"],
+                                                pool["cen"].astype(np.float64),
+                                                pool["wts"].astype(np.float64), 2, pool["d_off"],
+                                                [0, len(r.cand_ids)], r.cand_ids)
         else:
             want = oracle.maxsim(qv, [0, nq], dv, pool["d_off"], [0, len(r.cand_ids)], r.cand_ids)
         by_id = dict(zip(r.cand_ids.tolist(), want.tolist()))
