@@ -7,8 +7,9 @@
 //   q_i . x_j = q_i . C[id_j] + q_i . r_j.
 // The first term does not depend on the document, so one small MFMA kernel
 // tabulates P[c, (a, t)] = C[c] . q_t of query a for every centroid c (FP32,
-// in the caller's workspace; each query owns QW = 16 * ceil(max_len / 16)
-// columns, zero past its last token). The fused kernel then reads each
+// in the caller's workspace; each query owns QW = 16 * NQB columns, NQB the
+// 16-token blocks of the longest query rounded up to a power of two, zero
+// past its last token). The fused kernel then reads each
 // document token's id (4 B) and packed residual (dim * NBITS / 8 B) once from
 // HBM, decodes the residual codes into FP16 through a byte-indexed table in
 // LDS, and computes q_t . r_j with v_mfma_f32_16x16x32_f16 whose accumulator
@@ -103,11 +104,8 @@ struct ResWords {
       }
     }
   }
-  __device__ void zero() {
-#pragma unroll
-    for (int i = 0; i < N; ++i) w[i] = 0;
-  }
-  // byte j of the lane's piece, times `scale` (a power of two: the LUT entry size)
+  // byte j of the lane's piece shifted left by scale_log2 (a byte offset into
+  // the LUT, whose entries are 2^scale_log2 bytes)
   __device__ uint32_t byte_offset(int j, int scale_log2) const {
     return __builtin_amdgcn_ubfe(w[j >> 2], 8 * (j & 3), 8) << scale_log2;
   }
