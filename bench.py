@@ -223,7 +223,9 @@ def gen_docs(n_tokens, dim, dtype, seed, sample_rows=None):
 
 def autotune_extra(wl, cache):
     """Tunes the keys the other sections use: FP16 d = 128 at query capacities
-    16 and 64 (serving batches), and BF16 at d in {64, 256, 512, 768}."""
+    16 and 64 (serving batches) and eight 16-column blocks per unit (four
+    32-token queries scored in one launch), and BF16 at d in {64, 256, 512,
+    768}."""
     import torch
     import paper_2606_26439_amd as M
     import workloads as W
@@ -234,6 +236,12 @@ def autotune_extra(wl, cache):
         Q = M.Tokens(qt, torch.tensor([0, nq], device="cuda"), "f16", None, max_len=nq)
         rep = M.autotune(Q, D, reps=10, cache_path=cache)
         log(f"[autotune] f16 nq={nq}: best {rep['best']}")
+    q = W.unit_tokens(4 * 32, wl.dim, W.rng(1))
+    qt, _ = M.quantize(torch.from_numpy(q).cuda(), "f16")
+    Q = M.Tokens(qt, torch.arange(5, device="cuda", dtype=torch.int64) * 32, "f16", None,
+                 max_len=32)
+    rep = M.autotune(Q, D, reps=10, cache_path=cache)
+    log(f"[autotune] f16 4 x 32 query tokens: best {rep['best']}")
     B, nd, nq = 200_000, 128, 32
     for d in (64, 256, 512, 768):
         tok, _, _ = gen_docs(B * nd, d, "bf16", seed=3000 + d)
