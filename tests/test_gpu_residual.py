@@ -177,6 +177,17 @@ def test_residual_no_documents_and_workspace_checks():
     assert M.residual_score(Q, empty).numel() == 0
 
 
+def test_residual_documents_without_tokens():
+    # five documents, none with a token (no id or code arrays at all): -inf
+    # for a query with tokens, 0 for an empty query
+    c = _case(40, 128, 2, 64, seed=13, nq_lens=[32, 0])
+    Q, D = _device(c)
+    empty = M.ResidualDocs(D.centroids, D.weights, D.centroid_ids[:0], D.residuals[:0],
+                           torch.zeros(6, dtype=torch.int64, device="cuda"), 2)
+    got = M.residual_score(Q, empty).cpu().numpy()
+    assert np.all(np.isneginf(got[:5])) and np.all(got[5:] == 0.0)
+
+
 def test_residual_validate_flags_bad_centroid_ids():
     c = _case(80, 128, 2, 64, seed=9, nq_lens=[32])
     Q, D = _device(c)
