@@ -242,7 +242,7 @@ def autotune_extra(wl, cache):
                  max_len=32)
     rep = M.autotune(Q, D, reps=10, cache_path=cache)
     log(f"[autotune] f16 4 x 32 query tokens: best {rep['best']}")
-    B, nd, nq = 200_000, 128, 32
+    B, nd, nq = 500_000, 128, 32
     for d in (64, 256, 512, 768):
         tok, _, _ = gen_docs(B * nd, d, "bf16", seed=3000 + d)
         q = W.unit_tokens(nq, d, W.rng(1))
@@ -395,7 +395,9 @@ def bench_dim_tiling(batch_sizes=(100_000, 250_000, 500_000), dims=(64, 256, 512
             Q = M.Tokens(qt, torch.tensor([0, nq], device="cuda"), "bf16", None, max_len=nq)
             D = M.Tokens(tok, torch.from_numpy(d_off_np).cuda(), "bf16", None, max_len=nd)
             sc = torch.empty(B, dtype=torch.float32, device="cuda")
-            med, mean, std = time_fn(lambda: M.score(Q, D, out=sc), 10, 2)
+            # 5 warm-up launches: the first launches after the data is written
+            # run slow
+            med, mean, std = time_fn(lambda: M.score(Q, D, out=sc), 20, 5)
             b = R.fused_bytes(T, B, B, nq, d, "bf16")
             got = sc.cpu().numpy()[samp].astype(np.float64)
             qv, _ = oracle.exact_values(q, "bf16")
