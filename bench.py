@@ -302,7 +302,7 @@ def bench_multi_query(wl, counts=(1, 2, 4, 8), nq=32, steps=10):
         Q = M.Tokens(qt, torch.from_numpy(np.arange(n + 1, dtype=np.int64) * nq).cuda(), "f16",
                      None, max_len=nq)
         sc = torch.empty(n * wl.n_docs, dtype=torch.float32, device="cuda")
-        med, mean, std = time_fn(lambda: M.score(Q, D, out=sc), steps, 2)
+        med, mean, std = time_fn(lambda: M.score(Q, D, out=sc), steps, 5)
         rec = {"queries": n, "nq": nq, "ms_median": med,
                "query_doc_pairs_per_s": n * wl.n_docs / (med * 1e-3),
                "doc_bytes_per_s": wl.alg_bytes("f16") / (med * 1e-3)}
@@ -345,8 +345,8 @@ def bench_full_corpus(n_docs=8_841_823, nq=32, k=1000, steps=5):
         M.score(Q, D, out=sc)
         M.topk(sc, seg, k, workspace=ws)
 
-    med, mean, std = time_fn(step, steps, 1)
-    med_s, _, _ = time_fn(lambda: M.score(Q, D, out=sc), steps, 1)
+    med, mean, std = time_fn(step, steps, 3)
+    med_s, _, _ = time_fn(lambda: M.score(Q, D, out=sc), steps, 3)
     b = R.fused_bytes(T, n_docs, n_docs, nq, 128, "f16")
     got = sc[torch.from_numpy(samp).cuda()].cpu().numpy().astype(np.float64)
     qv, _ = oracle.exact_values(q, "f16")
@@ -366,7 +366,7 @@ def bench_full_corpus(n_docs=8_841_823, nq=32, k=1000, steps=5):
     Q8 = M.Tokens(q8t, torch.from_numpy(np.arange(n8 + 1, dtype=np.int64) * 16).cuda(), "f16",
                   None, max_len=16)
     sc8 = torch.empty(n8 * n_docs, dtype=torch.float32, device="cuda")
-    med8, _, _ = time_fn(lambda: M.score(Q8, D, out=sc8), steps, 1)
+    med8, _, _ = time_fn(lambda: M.score(Q8, D, out=sc8), steps, 3)
     rec.update({"batch8x16_ms": med8, "batch8x16_query_doc_pairs_per_s": n8 * n_docs / (med8 * 1e-3)})
     log(f"[bench] full corpus, 8 queries x 16 tokens in one launch: {med8:.2f} ms")
     del sc8, tok, D
@@ -828,7 +828,7 @@ def main():
         ceil = {}
         for v, name in ((0, "contiguous"), (1, "contiguous_nontemporal"), (2, "fused_tile_pattern"),
                         (3, "fused_tile_pattern_nontemporal"), (4, "contiguous_nontemporal_to_lds")):
-            med, _, _ = time_fn(lambda: M.stream_probe(D.tokens, v), 10, 2)
+            med, _, _ = time_fn(lambda: M.stream_probe(D.tokens, v), 10, 5)
             ceil[name] = D.tokens.numel() * 2 / (med * 1e-3) / 1e9
         best = max(ceil.values())
         out["roofline"]["measured_read_ceiling_GBps"] = ceil
@@ -893,10 +893,10 @@ def main():
 
     if not args.quick and not args.profile and "unfused" not in skip:
         top_f16 = set(torch.topk(scores, 100).indices.cpu().numpy().tolist())
-        fused_med = time_fn(lambda: M.score(Q, D, out=scores), 10, 2)[0]
+        fused_med = time_fn(lambda: M.score(Q, D, out=scores), 10, 5)[0]
         ws = torch.empty(M.unfused_workspace_bytes(Q, D), dtype=torch.uint8, device="cuda")
         su = torch.empty(wl.n_docs, dtype=torch.float32, device="cuda")
-        med, mean, std = time_fn(lambda: M.score_unfused(Q, D, out=su, workspace=ws), 10, 2)
+        med, mean, std = time_fn(lambda: M.score_unfused(Q, D, out=su, workspace=ws), 10, 5)
         bu = wl.alg_bytes("f16", unfused=True)
         top_u = set(torch.topk(su, 100).indices.cpu().numpy().tolist())
         out["unfused"] = {"ms_median": med, "docs_per_s": wl.n_docs / (med * 1e-3),
