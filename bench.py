@@ -313,6 +313,31 @@ def bench_multi_query(wl, counts=(1, 2, 4, 8), nq=32, steps=10):
     return out
 
 
+def bench_query_tokens(wl, nqs=(8, 16, 32, 64), steps=20):
+    """One query of Nq tokens against the 1M docs, Nq in {8, 16, 32, 64} (the
+    paper's query-token scaling), FP16."""
+    import torch
+    import paper_2606_26439_amd as M
+    import workloads as W
+    from paper_2606_26439_amd import roofline as R
+    _, D = wl.tokens("f16")
+    out = []
+    for nq in nqs:
+        q = W.unit_tokens(nq, wl.dim, W.rng(6))
+        qt, _ = M.quantize(torch.from_numpy(q).cuda(), "f16")
+        Q = M.Tokens(qt, torch.tensor([0, nq], device="cuda"), "f16", None, max_len=nq)
+        sc = torch.empty(wl.n_docs, dtype=torch.float32, device="cuda")
+        med, _, _ = time_fn(lambda: M.score(Q, D, out=sc), steps, 5)
+        b = R.fused_bytes(wl.T, wl.n_docs, wl.n_docs, nq, wl.dim, "f16")
+        rec = {"nq": nq, "ms_median": med, "docs_per_s": wl.n_docs / (med * 1e-3),
+               "hbm_frac": b / (med * 1e-3) / HBM_PEAK}
+        log(f"[bench] Nq = {nq}: {med:.3f} ms, {rec['docs_per_s'] / 1e6:.0f} M docs/s, "
+            f"{rec['hbm_frac'] * 100:.1f}% HBM")
+        out.append(rec)
+        del sc
+    return out
+
+
 def bench_full_corpus(n_docs=8_841_823, nq=32, k=1000, steps=5):
     """Exhaustive retrieval at MS MARCO passage-collection scale (8.8M
     synthetic FP16 docs, lognormal lengths, ~156 GB): one 32-token query
@@ -752,7 +777,7 @@ def main():
                     default=None,
                     help="run one secondary section alone and print its JSON")
     ap.add_argument("--skip", default="", help="comma list of sections to skip: "
-                    "plain,forms,multi,unfused,pq,pq16,residual,dims,serving,corpus")
+                    "plain,forms,multi,nq,unfused,pq,pq16,residual,dims,serving,corpus")
     ap.add_argument("--cpu-sample", type=int, default=140000,
                     help="docs for the oracle timing (about 10 s of one core)")
     ap.add_argument("--profile", action="store_true",
@@ -924,6 +949,8 @@ def main():
 
     if not args.quick and not args.profile and "multi" not in skip:
         out["multi_query"] = bench_multi_query(wl)
+    if not args.quick and not args.profile and "nq" not in skip:
+        out["query_tokens"] = bench_query_tokens(wl)
 
     if not args.quick and not args.profile and "unfused" not in skip:
         top_f16 = set(torch.topk(scores, 100).indices.cpu().numpy().tolist())
