@@ -338,6 +338,36 @@ def bench_query_tokens(wl, nqs=(8, 16, 32, 64), steps=20):
     return out
 
 
+def bench_doc_tokens(nds=(32, 64, 128, 256, 512), tokens=1 << 26, nq=32, steps=20):
+    """Fixed document length Nd in {32, ..., 512} (the paper's document-token
+    scaling) at 64M tokens per launch, FP16, one 32-token query."""
+    import torch
+    import paper_2606_26439_amd as M
+    import workloads as W
+    from paper_2606_26439_amd import roofline as R
+    q = W.unit_tokens(nq, 128, W.rng(1))
+    qt, _ = M.quantize(torch.from_numpy(q).cuda(), "f16")
+    Q = M.Tokens(qt, torch.tensor([0, nq], device="cuda"), "f16", None, max_len=nq)
+    tok, _, _ = gen_docs(tokens, 128, "f16", seed=9000)
+    out = []
+    for nd in nds:
+        B = tokens // nd
+        D = M.Tokens(tok, torch.arange(B + 1, device="cuda", dtype=torch.int64) * nd, "f16", None,
+                     max_len=nd)
+        sc = torch.empty(B, dtype=torch.float32, device="cuda")
+        med, _, _ = time_fn(lambda: M.score(Q, D, out=sc), steps, 5)
+        b = R.fused_bytes(tokens, B, B, nq, 128, "f16")
+        rec = {"nd": nd, "n_docs": B, "ms_median": med, "docs_per_s": B / (med * 1e-3),
+               "hbm_frac": b / (med * 1e-3) / HBM_PEAK}
+        log(f"[bench] Nd = {nd} ({B} docs): {med:.3f} ms, {rec['docs_per_s'] / 1e6:.0f} M docs/s, "
+            f"{rec['hbm_frac'] * 100:.1f}% HBM")
+        out.append(rec)
+        del sc, D
+    del tok
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_full_corpus(n_docs=8_841_823, nq=32, k=1000, steps=5):
     """Exhaustive retrieval at MS MARCO passage-collection scale (8.8M
     synthetic FP16 docs, lognormal lengths, ~156 GB): one 32-token query
@@ -777,7 +807,7 @@ def main():
                     default=None,
                     help="run one secondary section alone and print its JSON")
     ap.add_argument("--skip", default="", help="comma list of sections to skip: "
-                    "plain,forms,multi,nq,unfused,pq,pq16,residual,dims,serving,corpus")
+                    "plain,forms,multi,nq,nd,unfused,pq,pq16,residual,dims,serving,corpus")
     ap.add_argument("--cpu-sample", type=int, default=140000,
                     help="docs for the oracle timing (about 10 s of one core)")
     ap.add_argument("--profile", action="store_true",
@@ -951,6 +981,8 @@ def main():
         out["multi_query"] = bench_multi_query(wl)
     if not args.quick and not args.profile and "nq" not in skip:
         out["query_tokens"] = bench_query_tokens(wl)
+    if not args.quick and not args.profile and "nd" not in skip:
+        out["doc_tokens"] = bench_doc_tokens()
 
     if not args.quick and not args.profile and "unfused" not in skip:
         top_f16 = set(torch.topk(scores, 100).indices.cpu().numpy().tolist())
