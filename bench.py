@@ -340,7 +340,8 @@ def bench_query_tokens(wl, nqs=(8, 16, 32, 64), steps=20):
 
 def bench_doc_tokens(nds=(32, 64, 128, 256, 512), tokens=1 << 26, nq=32, steps=20):
     """Fixed document length Nd in {32, ..., 512} (the paper's document-token
-    scaling) at 64M tokens per launch, FP16, one 32-token query."""
+    scaling) at 64M tokens per launch, then batch sizes 1K-500K at Nd = 128
+    (its batch-size table); FP16, one 32-token query."""
     import torch
     import paper_2606_26439_amd as M
     import workloads as W
@@ -349,7 +350,7 @@ def bench_doc_tokens(nds=(32, 64, 128, 256, 512), tokens=1 << 26, nq=32, steps=2
     qt, _ = M.quantize(torch.from_numpy(q).cuda(), "f16")
     Q = M.Tokens(qt, torch.tensor([0, nq], device="cuda"), "f16", None, max_len=nq)
     tok, _, _ = gen_docs(tokens, 128, "f16", seed=9000)
-    out = []
+    out = {"fixed_nd": [], "batch": []}
     for nd in nds:
         B = tokens // nd
         D = M.Tokens(tok, torch.arange(B + 1, device="cuda", dtype=torch.int64) * nd, "f16", None,
@@ -361,7 +362,21 @@ def bench_doc_tokens(nds=(32, 64, 128, 256, 512), tokens=1 << 26, nq=32, steps=2
                "hbm_frac": b / (med * 1e-3) / HBM_PEAK}
         log(f"[bench] Nd = {nd} ({B} docs): {med:.3f} ms, {rec['docs_per_s'] / 1e6:.0f} M docs/s, "
             f"{rec['hbm_frac'] * 100:.1f}% HBM")
-        out.append(rec)
+        out["fixed_nd"].append(rec)
+        del sc, D
+    # batch scaling at Nd = 128 (the paper's batch-size table): from launch-
+    # latency-bound small batches to the HBM regime
+    for B in (1_000, 5_000, 10_000, 50_000, 100_000, 200_000, 500_000):
+        D = M.Tokens(tok[:B * 128], torch.arange(B + 1, device="cuda", dtype=torch.int64) * 128,
+                     "f16", None, max_len=128)
+        sc = torch.empty(B, dtype=torch.float32, device="cuda")
+        med, _, _ = time_fn(lambda: M.score(Q, D, out=sc), 50, 5)
+        b = R.fused_bytes(B * 128, B, B, nq, 128, "f16")
+        rec = {"n_docs": B, "ms_median": med, "docs_per_s": B / (med * 1e-3),
+               "hbm_frac": b / (med * 1e-3) / HBM_PEAK}
+        log(f"[bench] B = {B} (Nd = 128): {med * 1e3:.1f} us, {rec['docs_per_s'] / 1e6:.0f} M docs/s, "
+            f"{rec['hbm_frac'] * 100:.1f}% HBM")
+        out["batch"].append(rec)
         del sc, D
     del tok
     torch.cuda.empty_cache()
