@@ -931,7 +931,8 @@ def main():
         # measured read ceiling on the same 17.8 GB of FP16 document tokens
         ceil = {}
         for v, name in ((0, "contiguous"), (1, "contiguous_nontemporal"), (2, "fused_tile_pattern"),
-                        (3, "fused_tile_pattern_nontemporal"), (4, "contiguous_nontemporal_to_lds")):
+                        (3, "fused_tile_pattern_nontemporal"), (4, "contiguous_nontemporal_to_lds"),
+                        (5, "round_robin_tiles_nontemporal_to_lds")):
             med, _, _ = time_fn(lambda: M.stream_probe(D.tokens, v), 10, 5)
             ceil[name] = D.tokens.numel() * 2 / (med * 1e-3) / 1e9
         best = max(ceil.values())

@@ -357,7 +357,8 @@ maxsim_status maxsim_check(const int32_t* flags, maxsim_stream_t stream);
  *   variant 0: lane-contiguous loads; 1: the same, non-temporal;
  *           2: the fused scorer's 16-row tile pattern; 3: the same,
  *           non-temporal; 4: lane-contiguous non-temporal loads straight
- *           into LDS, read back from LDS.
+ *           into LDS, read back from LDS; 5: variant 4 with 4 KiB tiles
+ *           dealt round-robin to the waves instead of one share per wave.
  */
 maxsim_status maxsim_stream_probe(const void* buf, size_t bytes, int32_t variant, uint32_t* sink,
                                   int64_t sink_len, maxsim_stream_t stream);

@@ -1009,7 +1009,7 @@ maxsim_status maxsim_stream_probe(const void* buf, size_t bytes, int32_t variant
                                   int64_t sink_len, maxsim_stream_t stream) {
   if (!buf || !sink) return fail(MAXSIM_EINVAL, "stream_probe: NULL buffer");
   if (!aligned(buf, 16)) return fail(MAXSIM_EINVAL, "stream_probe: buffer must be 16-byte aligned");
-  if (variant < 0 || variant > 4) return fail(MAXSIM_EINVAL, "stream_probe: variant must be in [0, 4]");
+  if (variant < 0 || variant > 5) return fail(MAXSIM_EINVAL, "stream_probe: variant must be in [0, 5]");
   if (sink_len < 4) return fail(MAXSIM_EINVAL, "stream_probe: sink needs at least 4 entries");
   int64_t grid = std::min<int64_t>(sink_len / 4, (int64_t)device_info().cus * 8);
   hipError_t e = launch_stream_probe(buf, bytes, variant, sink, (int)grid, (hipStream_t)stream);

@@ -12,6 +12,9 @@
 //   variant 3: variant 2 with the non-temporal hint
 //   variant 4: lane-contiguous non-temporal loads straight into LDS
 //              (global_load_lds_dwordx4), read back with ds_read_b128
+//   variant 5: variant 4 with the 4 KiB tiles dealt round-robin to the waves
+//              (all waves sweep the buffer together) instead of one
+//              contiguous share per wave
 #include "device_common.h"
 #include "kernels.h"
 
@@ -55,8 +58,11 @@ __global__ __launch_bounds__(256) void stream_read_kernel(const u32x4* __restric
   if (lane == 0) sink[w] = x;
 }
 
-// Variant 4: each wave owns a ring of 4 tiles (4 KiB each) in LDS; tile t+3
-// is requested while tile t is read back.
+// Variants 4 and 5: each wave owns a ring of 4 tiles (4 KiB each) in LDS;
+// its tile i+3 is requested while tile i is read back. The wave's tiles are
+// its i-th local tiles: a contiguous share (variant 4) or every nw-th tile
+// starting at its index (variant 5).
+template <bool ROUND_ROBIN>
 __global__ __launch_bounds__(256) void stream_read_lds_kernel(const u32x4* __restrict__ buf,
                                                               int64_t n16,
                                                               uint32_t* __restrict__ sink) {
@@ -66,13 +72,23 @@ __global__ __launch_bounds__(256) void stream_read_lds_kernel(const u32x4* __res
   const int64_t nw = (int64_t)gridDim.x * 4;
   const int64_t w = (int64_t)blockIdx.x * 4 + wv;
   const int64_t tiles = n16 / 256;
-  const int64_t t_lo = tiles * w / nw, t_hi = tiles * (w + 1) / nw;
+  // local tile indices [t_lo, t_hi) and their buffer tiles
+  int64_t t_lo, t_hi;
+  if constexpr (ROUND_ROBIN) {
+    t_lo = 0;
+    t_hi = w < tiles ? (tiles - w + nw - 1) / nw : 0;
+  } else {
+    t_lo = tiles * w / nw;
+    t_hi = tiles * (w + 1) / nw;
+  }
+  auto tile_of = [&](int64_t t) -> int64_t { return ROUND_ROBIN ? w + t * nw : t; };
   u32x4 acc = {0, 0, 0, 0};
   auto issue = [&](int64_t t, int slot) {
     if (t >= t_hi) t = t_hi - 1;
+    const int64_t bt = tile_of(t);
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-      __builtin_amdgcn_global_load_lds((const void*)(buf + t * 256 + c * 64 + lane),
+      __builtin_amdgcn_global_load_lds((const void*)(buf + bt * 256 + c * 64 + lane),
                                        (__attribute__((address_space(3))) void*)&ring[wv][slot][c * 64],
                                        16, 0, 2 /* nt */);
   };
@@ -115,8 +131,12 @@ hipError_t launch_stream_probe(const void* buf, size_t bytes, int variant, uint3
                          n16, sink);
       break;
     case 4:
-      hipLaunchKernelGGL(stream_read_lds_kernel, dim3(grid), dim3(256), 0, s, (const u32x4*)buf,
-                         n16, sink);
+      hipLaunchKernelGGL(stream_read_lds_kernel<false>, dim3(grid), dim3(256), 0, s,
+                         (const u32x4*)buf, n16, sink);
+      break;
+    case 5:
+      hipLaunchKernelGGL(stream_read_lds_kernel<true>, dim3(grid), dim3(256), 0, s,
+                         (const u32x4*)buf, n16, sink);
       break;
     default:
       hipLaunchKernelGGL(stream_read_kernel<0>, dim3(grid), dim3(256), 0, s, (const u32x4*)buf,
