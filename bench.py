@@ -724,7 +724,8 @@ def bench_serving(n_pool=5_000_000, fractions=(0.25, 0.5, 0.75, 0.9), n_req=10_0
     gc.disable()  # no collector pauses inside the timed runs
 
     def run(reqs, arrivals):
-        sched = S.Scheduler(128, k, max_inflight=3, mem_budget=8 << 30)
+        sched = S.Scheduler(128, k, max_inflight=3, mem_budget=8 << 30,
+                            residual_centroids=n_cen)
         srv = S.Server(sched, backend)
         start = time.perf_counter() + 0.01
         for r, a in zip(reqs, arrivals):

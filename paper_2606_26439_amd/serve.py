@@ -3,8 +3,8 @@
 Requests (a query's token vectors plus a candidate id list) arrive at any
 time. The scheduler admits queued requests into the next batch whenever an
 execution slot is free and the batch's device memory fits the budget; a
-batch is one multi-query launch of the fused scorer (or the fused PQ scorer)
-followed by per-request top-k, enqueued on its own HIP stream, so batches
+batch is one multi-query launch of the fused scorer (or the fused PQ scorer,
+or the residual-compressed scorer) followed by per-request top-k, enqueued on its own HIP stream, so batches
 formed while earlier ones are still on the GPU overlap with them. Every score
 is produced by one wavefront with a fixed reduction order, so a request's
 result does not depend on which batch carried it.
@@ -67,8 +67,12 @@ class Scheduler:
 
     def __init__(self, dim: int, k: int = 100, max_inflight: int = 2,
                  mem_budget: int = 4 << 30, max_batch_requests: int = 64,
-                 max_batch_pairs: int = 4_000_000, max_queue: int = 100_000):
+                 max_batch_pairs: int = 4_000_000, max_queue: int = 100_000,
+                 residual_centroids: int = 0):
         self.dim, self.k = dim, k
+        # a residual-mode request also holds its columns of the centroid-query
+        # table: up to 64 (the query-token bound) FP32 entries per centroid
+        self.residual_table_bytes = residual_centroids * 64 * 4
         self.max_inflight = max_inflight
         self.mem_budget = mem_budget
         self.max_batch_requests = max_batch_requests
@@ -80,7 +84,10 @@ class Scheduler:
         self._next_bid = 0
 
     def cost(self, r: Request) -> int:
-        return request_bytes(len(r.query), len(r.cand_ids), self.dim, self.k)
+        c = request_bytes(len(r.query), len(r.cand_ids), self.dim, self.k)
+        if r.mode == "residual":
+            c += self.residual_table_bytes
+        return c
 
     def submit(self, r: Request) -> bool:
         """Queues a request; rejects one that can never fit or a full queue."""

@@ -187,3 +187,19 @@ def test_latency_stats():
         r.status, r.done_at = "done", (i + 1) * 1e-3
     st = S.latency_stats(rs)
     assert st["n"] == 100 and abs(st["p50_ms"] - 50.5) < 1e-6 and st["p99_ms"] > 99
+
+
+def test_residual_requests_are_charged_for_their_table_columns():
+    # a residual-mode request also holds up to 64 FP32 table entries per
+    # centroid; exact and PQ requests do not
+    sched = S.Scheduler(64, 10, mem_budget=1 << 30, residual_centroids=1000)
+    q = np.zeros((6, 64), np.float32)
+    ids = np.arange(80, dtype=np.int32)
+    base = S.request_bytes(6, 80, 64, 10)
+    assert sched.cost(S.Request(0, q, ids, mode="exact")) == base
+    assert sched.cost(S.Request(1, q, ids, mode="pq")) == base
+    assert sched.cost(S.Request(2, q, ids, mode="residual")) == base + 1000 * 64 * 4
+    # a budget that fits the request but not its table rejects it
+    tight = S.Scheduler(64, 10, mem_budget=base + 1000, residual_centroids=1000)
+    r = S.Request(3, q, ids, mode="residual")
+    assert not tight.submit(r) and r.status == "rejected"
