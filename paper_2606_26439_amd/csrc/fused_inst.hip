@@ -60,8 +60,7 @@ FusedFns pick_q(int qm, int rt) {
                 occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_SHARED, STAGE>, STAGE};
       return {nullptr, nullptr, STAGE};
     }
-  }
-  if constexpr (NQB == 8) {
+  } else if constexpr (NQB == 8) {
     // eight query blocks only with the query operand in VGPRs, and only for
     // 1- and 2-byte elements (the host never asks for anything else)
     if constexpr (DT == DT_F32) {
@@ -71,15 +70,16 @@ FusedFns pick_q(int qm, int rt) {
       return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE>,
               occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE>, STAGE};
     }
+  } else {
+    if (qm == fused_detail::Q_REGS)
+      return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE>,
+              occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE>, STAGE};
+    if (qm == fused_detail::Q_WAVE)
+      return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_WAVE, STAGE>,
+              occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_WAVE, STAGE>, STAGE};
+    return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_SHARED, STAGE>,
+            occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_SHARED, STAGE>, STAGE};
   }
-  if (qm == fused_detail::Q_REGS)
-    return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE>,
-            occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_REGS, STAGE>, STAGE};
-  if (qm == fused_detail::Q_WAVE)
-    return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_WAVE, STAGE>,
-            occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_WAVE, STAGE>, STAGE};
-  return {launch_fused_t<NQB, DCH, PF, NW, fused_detail::Q_SHARED, STAGE>,
-          occupancy_fused_t<NQB, DCH, PF, NW, fused_detail::Q_SHARED, STAGE>, STAGE};
 }
 
 template <int NQB, int DCH, int PF, bool STAGE>

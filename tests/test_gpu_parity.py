@@ -187,6 +187,7 @@ def test_every_launch_configuration_is_bit_identical(tmp_path, dtype, dim):
     # arithmetic, so the same bits.
     q, q_off, d, d_off = _ragged(90, dim, seed=dim + 61, nq_lens=[32, 7, 64, 16], empty_every=29)
     Q = device_tokens(q, q_off, dtype)
+    Q2 = device_tokens(q[q_off[2]:], q_off[2:] - q_off[2], dtype)
     D = device_tokens(d, d_off, dtype)
     want = o1_scores(q, q_off, d, d_off, dtype)
     configs = [(stage, pf, nw, 16) for stage in (0, 1) for pf in (2, 3, 4) for nw in (4, 8)]
@@ -205,6 +206,10 @@ def test_every_launch_configuration_is_bit_identical(tmp_path, dtype, dim):
                 ref = got
                 assert_close_o1(got, want, f"{dtype} d={dim}", dtype)
             assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (stage, pf, nw, rows)
+            # the last two queries alone give the same bits
+            got2 = M.score(Q2, D).cpu().numpy()
+            assert np.array_equal(got2.view(np.uint32), ref[2 * 90:].view(np.uint32)), (
+                stage, pf, nw, rows)
     finally:
         _force_cfg(tmp_path, dtype, dim, 0, 2 if dtype == "f32" else 4, 4)
         M.load_tune_cache(M.default_tune_cache())
@@ -251,6 +256,23 @@ def test_grouped_queries_share_document_reads(dtype, dim):
         Qa = device_tokens(q[q_off[a]:q_off[a + 1]], [0, nq_lens[a]], dtype, max_len=16)
         alone = M.score(Qa, D).cpu().numpy()
         assert np.array_equal(alone.view(np.uint32), got[a * 140:(a + 1) * 140].view(np.uint32)), a
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16", "fp8"])
+def test_32_token_queries_share_document_reads(dtype):
+    # 11 queries of at most 32 tokens at d = 128: units of 4 + 4 + 3 queries
+    # (8 query blocks each; one empty query, ragged lengths)
+    nq_lens = [32, 17, 0, 32, 5, 31, 32, 16, 1, 32, 24]
+    q, q_off, d, d_off = _ragged(150, 128, seed=83, nq_lens=nq_lens, empty_every=19)
+    Q = device_tokens(q, q_off, dtype, max_len=32)
+    D = device_tokens(d, d_off, dtype)
+    got = M.score(Q, D).cpu().numpy()
+    want = o1_scores(q, q_off, d, d_off, dtype)
+    assert_close_o1(got, want, f"four per unit {dtype}", dtype)
+    for a in (0, 2, 7, 10):
+        Qa = device_tokens(q[q_off[a]:q_off[a + 1]], [0, nq_lens[a]], dtype, max_len=32)
+        alone = M.score(Qa, D).cpu().numpy()
+        assert np.array_equal(alone.view(np.uint32), got[a * 150:(a + 1) * 150].view(np.uint32)), a
 
 
 def test_understated_length_poisons_only_that_query():
