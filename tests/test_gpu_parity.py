@@ -73,6 +73,19 @@ def test_fused_query_capacities(nq):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("dim", [192, 1024])
+def test_fused_dimension_edges(dtype, dim):
+    # d = 192: three 64-wide chunks (not a multiple of 128); d = 1024: the
+    # largest supported width (the query blocks fill the LDS beside the ring)
+    q, q_off, d, d_off = _ragged(70, dim, seed=dim + 5, nq_lens=[32, 9], empty_every=31)
+    Q = device_tokens(q, q_off, dtype)
+    D = device_tokens(d, d_off, dtype)
+    got = M.score(Q, D).cpu().numpy()
+    want = o1_scores(q, q_off, d, d_off, dtype)
+    assert_close_o1(got, want, f"{dtype} d={dim}", dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_fused_candidates(dtype):
     q, q_off, d, d_off = _ragged(400, 128, seed=11, nq_lens=[8, 64, 20, 1, 40], empty_every=50)
     cand_off, cand_ids = W.candidates(5, 400, seed=4, size_range=(10, 300))
