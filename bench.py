@@ -29,8 +29,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "docs/sec + % HBM peak, fused vs unfused at fixed accuracy; p50/p99 @ QPS"
 HBM_PEAK = 8.0e12
+# the fused kernel's sources and the build script that holds its compile flags
 KERNEL_SOURCES = ["paper_2606_26439_amd/csrc/fused_impl.h", "paper_2606_26439_amd/csrc/fused_inst.hip",
-                  "paper_2606_26439_amd/csrc/device_common.h"]
+                  "paper_2606_26439_amd/csrc/device_common.h", "paper_2606_26439_amd/build.py"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_f16_1M_ragged_traffic.json")
 
 

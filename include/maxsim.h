@@ -75,6 +75,8 @@ typedef enum {
  *             exceeds it on the device gets NaN scores.
  *   scales    FP8 only: [n_tokens] FP32 per-token scales, each a normal power
  *             of two; the token's value is code * scale. NULL otherwise.
+ * Token values must be finite: a NaN or infinite element gives unspecified
+ * scores for the sets it meets (never an out-of-bounds access).
  */
 typedef struct {
   int32_t dtype;

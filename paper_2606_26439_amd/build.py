@@ -20,7 +20,14 @@ ARCH = "gfx950"
 
 # (source, object name, extra flags); the fused scorer is compiled once per
 # element type so the four instantiation sets build in parallel.
-SOURCES = [("fused_inst.hip", f"fused_dt{t}", [f"-DFUSED_DT={t}"]) for t in range(4)] + [
+# Token values are finite, so no NaN reaches the fused scorer's maxima: they
+# need no quieting of each matrix-core result before the max (the overlong-
+# query NaN is written as a bit pattern). Measured 3-5% faster for grouped
+# queries and FP8; the FP32 form (type 0) measured 1% slower and keeps the
+# default.
+SOURCES = [("fused_inst.hip", f"fused_dt{t}",
+            [f"-DFUSED_DT={t}"] + (["-fno-honor-nans"] if t != 0 else []))
+           for t in range(4)] + [
     ("fused_dispatch.cpp", "fused_dispatch", []),
     # NaN never reaches the PQ maxima (every table entry and every decoded
     # dot product is finite), so the maxima need no NaN canonicalisation

@@ -275,7 +275,8 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     // gq * n_docs (with candidate lists the unit is one query, sbase 0)
     const int64_t sbase = (P.cand_off == nullptr) ? a * (P.group - 1) * P.n_docs : 0;
     auto store = [&](int64_t pp, int gq, float v) {
-      if ((qmask >> (16 + gq)) & 1u) v = __builtin_nanf("");
+      // (NaN as a bit pattern: this file is compiled assuming no NaN arithmetic)
+      if ((qmask >> (16 + gq)) & 1u) v = __builtin_bit_cast(float, 0x7fc00000u);
       P.scores[pp + sbase + (int64_t)gq * P.n_docs] = v;
     };
 
