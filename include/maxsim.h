@@ -191,6 +191,9 @@ maxsim_status maxsim_score(const maxsim_csr* queries, const maxsim_csr* docs,
  * inside `workspace`, then a second kernel reads S back for the max over
  * document tokens and the sum over query tokens. Same arguments and results
  * as maxsim_score; candidates are not supported (EUNSUPPORTED).
+ * The workspace size is n_q * n_tokens * (16-column blocks of max_len) * 64
+ * bytes; when that overflows size_t the size call returns SIZE_MAX and the
+ * scoring call EUNSUPPORTED.
  */
 size_t maxsim_score_unfused_workspace_size(const maxsim_csr* queries, const maxsim_csr* docs);
 maxsim_status maxsim_score_unfused(const maxsim_csr* queries, const maxsim_csr* docs,

@@ -383,8 +383,14 @@ maxsim_status maxsim_score(const maxsim_csr* queries, const maxsim_csr* docs,
 }
 
 size_t maxsim_score_unfused_workspace_size(const maxsim_csr* q, const maxsim_csr* d) {
-  if (!q || !d) return 0;
-  return (size_t)q->n_sets * (size_t)d->n_tokens * (size_t)(nqb_for(q->max_len) * 16) * 4;
+  if (!q || !d || q->n_sets < 0 || d->n_tokens < 0) return 0;
+  // S holds n_q x n_tokens rows of the query-capacity columns, FP32
+  const size_t cols = (size_t)nqb_for(q->max_len) * 16 * 4;
+  size_t n = 0;
+  if (__builtin_mul_overflow((size_t)q->n_sets, (size_t)d->n_tokens, &n) ||
+      __builtin_mul_overflow(n, cols, &n))
+    return SIZE_MAX;
+  return n;
 }
 
 maxsim_status maxsim_score_unfused(const maxsim_csr* queries, const maxsim_csr* docs,
@@ -398,6 +404,7 @@ maxsim_status maxsim_score_unfused(const maxsim_csr* queries, const maxsim_csr* 
     pl.P.nch = queries->dim / 128;
   }
   size_t need = maxsim_score_unfused_workspace_size(queries, docs);
+  if (need == SIZE_MAX) return fail(MAXSIM_EUNSUPPORTED, "unfused: S exceeds the address space");
   if (need > 0 && (!workspace || ws_bytes < need))
     return fail(MAXSIM_EWORKSPACE, "unfused: workspace needs %zu bytes", need);
   if (pl.n_pairs == 0) return MAXSIM_OK;
@@ -555,6 +562,10 @@ maxsim_status plan_pq(const maxsim_csr* q, const maxsim_pq_docs* d, const maxsim
   // keep the LDS and VALU pipes busy (8 waves measured 1.7x slower).
   P.nw = 16;
   pl.lds = ((size_t)d->M * d->K * qt + (size_t)qt * q->dim) * 4;
+  // per-slice partial scores; a size past the address space is refused, not
+  // wrapped
+  if (n_slices > 1 && (size_t)n_pairs > SIZE_MAX / 4 / (size_t)n_slices)
+    return fail(MAXSIM_EUNSUPPORTED, "pq: partial scores exceed the address space");
   pl.ws = n_slices > 1 ? (size_t)n_slices * (size_t)n_pairs * 4 : 0;
   pl.variant = 0;
   return MAXSIM_OK;

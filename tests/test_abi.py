@@ -81,6 +81,11 @@ def test_pq_and_unfused_validation():
     assert need == 1 * 1000 * 16 * 4
     assert L.maxsim_score_unfused(ctypes.byref(qc), ctypes.byref(dc), ctypes.c_void_p(16), None, 0,
                                   None) == 3
+    # a size that overflows size_t is reported, never wrapped to a small one
+    huge = _csr(n_tokens=1 << 62)
+    assert L.maxsim_score_unfused_workspace_size(ctypes.byref(qc), ctypes.byref(huge)) == 2**64 - 1
+    assert L.maxsim_score_unfused(ctypes.byref(qc), ctypes.byref(huge), ctypes.c_void_p(16),
+                                  ctypes.c_void_p(256), 2**63, None) == 2
 
 
 def test_missing_tune_cache_is_a_no_op(tmp_path):
