@@ -820,7 +820,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="headline step only")
-    ap.add_argument("--only", choices=["pq", "pq16", "residual", "dims", "serving", "corpus"],
+    ap.add_argument("--only", choices=["pq", "pq16", "residual", "dims", "serving", "corpus",
+                                       "multi4"],
                     default=None,
                     help="run one secondary section alone and print its JSON")
     ap.add_argument("--skip", default="", help="comma list of sections to skip: "
@@ -852,7 +853,9 @@ def main():
     if args.only:
         fn = {"pq": bench_pq, "pq16": bench_pq_paper_shape, "residual": bench_residual,
               "dims": bench_dim_tiling, "serving": bench_serving,
-              "corpus": bench_full_corpus}[args.only]
+              "corpus": bench_full_corpus,
+              # four 32-token queries in one launch (the eight-block kernel)
+              "multi4": lambda: bench_multi_query(Workload(), counts=(4,))}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
 
