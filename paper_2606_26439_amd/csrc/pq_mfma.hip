@@ -22,6 +22,22 @@
 
 namespace {
 
+// Sum over the 16 lanes of each row (a query block's columns), left in every
+// lane of the row, by four DPP row rotations with adds: register to register,
+// so the LDS pipe this kernel is bound by stays free for the codebook reads.
+// Lane 0 adds the same pairs as an xor butterfly.
+__device__ __forceinline__ float sum_row16(float v) {
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128,
+                                                             0xF, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124,
+                                                             0xF, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x122,
+                                                             0xF, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x121,
+                                                             0xF, 0xF, false));
+  return v;
+}
+
 template <int M>
 struct PqCodes;
 template <>
@@ -237,10 +253,7 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
         if ((nb + 1) % bpq == 0) {
           const int gq = nb / bpq;
           float t = qsum;
-          t += xor_shfl(t, 8);
-          t += xor_shfl(t, 4);
-          t += xor_shfl(t, 2);
-          t += xor_shfl(t, 1);
+          t = sum_row16(t);
           if (lane == 0 && ((valid_m >> gq) & 1u)) store(pp, gq, t);
           qsum = 0.f;
         }
