@@ -26,6 +26,21 @@ namespace {
 // lane of the row, by four DPP row rotations with adds: register to register,
 // so the LDS pipe this kernel is bound by stays free for the codebook reads.
 // Lane 0 adds the same pairs as an xor butterfly.
+// Max over the four 16-lane rows (lanes i, i ^ 16, i ^ 32, i ^ 48), left in
+// every lane, without the LDS pipe: v_permlane16_swap exchanges odd and even
+// rows between two copies of v, v_permlane32_swap the two half-waves. Written
+// as assembly with explicit wait states on both sides, so the two swapped
+// copies stay distinct values for the compiler. The whole wave executes it.
+__device__ __forceinline__ float max_rows4(float v) {
+  float a = v, b = v;
+  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+  v = fmaxf(a, b);
+  a = v;
+  b = v;
+  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+  return fmaxf(a, b);
+}
+
 __device__ __forceinline__ float sum_row16(float v) {
   v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128,
                                                              0xF, 0xF, false));
@@ -245,9 +260,7 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
       float qsum = 0.f;
 #pragma unroll
       for (int nb = 0; nb < NQB; ++nb) {
-        float v = mx[nb];
-        v = fmaxf(v, xor_shfl(v, 16));
-        v = fmaxf(v, xor_shfl(v, 32));
+        const float v = max_rows4(mx[nb]);
         qsum += v;
         mx[nb] = -__builtin_inff();
         if ((nb + 1) % bpq == 0) {
