@@ -29,15 +29,23 @@ namespace {
 // Max over the four 16-lane rows (lanes i, i ^ 16, i ^ 32, i ^ 48), left in
 // every lane, without the LDS pipe: v_permlane16_swap exchanges odd and even
 // rows between two copies of v, v_permlane32_swap the two half-waves. Written
-// as assembly with explicit wait states on both sides, so the two swapped
-// copies stay distinct values for the compiler. The whole wave executes it.
+// as assembly so the two swapped copies stay distinct values for the
+// compiler. The compiler's hazard recognizer does not look inside inline
+// assembly, so the block carries its own wait states. The CDNA4 ISA's table
+// of manually inserted wait states requires, before a V_PERMLANE16_SWAP or
+// V_PERMLANE32_SWAP, 2 wait states after a VALU write of a VGPR it reads and
+// 4 after a V_CMPX write of EXEC; "s_nop 3" gives 4, covering both whatever
+// the compiler schedules before the block. The "s_nop 1" after it keeps the
+// swapped values two states away from their first reader. The whole wave
+// executes it. (A CPU test builds this file to gfx950 assembly and checks
+// the wait states and that the max after each swap reads both registers.)
 __device__ __forceinline__ float max_rows4(float v) {
   float a = v, b = v;
-  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+  asm volatile("s_nop 3\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
   v = fmaxf(a, b);
   a = v;
   b = v;
-  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+  asm volatile("s_nop 3\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
   return fmaxf(a, b);
 }
 

@@ -44,12 +44,23 @@ class Request:
         return None if self.done_at is None else self.done_at - self.arrival
 
 
-def request_bytes(nq: int, n_cand: int, dim: int, k: int, elem: int = 2) -> int:
+def topk_workspace_per_request(k: int) -> int:
+    """Bytes of top-k workspace one request's segment needs, as the library
+    sizes it (maxsim_topk_workspace_size for one segment; a host call, no
+    device needed)."""
+    from . import _binding as B
+    return B.topk_workspace_bytes(1, k)
+
+
+def request_bytes(nq: int, n_cand: int, dim: int, k: int, elem: int = 2,
+                  topk_ws: Optional[int] = None) -> int:
     """Device bytes a request occupies while in flight: query tokens (FP32
-    staging + converted copy), candidate ids, scores, top-k outputs and the
-    per-segment top-k workspace."""
-    topk_ws = 8 * 256 * 4 + 256 + 8 * k
-    return (nq * dim * (4 + elem) + 8 * n_cand + 16 + 8 * k + topk_ws + 8)
+    staging + converted copy), candidate ids and scores, its query and
+    candidate offsets, top-k outputs and its segment of the top-k workspace
+    (the library's own figure unless `topk_ws` is given)."""
+    if topk_ws is None:
+        topk_ws = topk_workspace_per_request(k)
+    return nq * dim * (4 + elem) + 8 * n_cand + 16 + 8 * k + topk_ws + 8
 
 
 @dataclasses.dataclass
@@ -70,6 +81,7 @@ class Scheduler:
                  max_batch_pairs: int = 4_000_000, max_queue: int = 100_000,
                  residual_centroids: int = 0):
         self.dim, self.k = dim, k
+        self.topk_ws = topk_workspace_per_request(k)
         # a residual-mode request also holds its columns of the centroid-query
         # table: up to 64 (the query-token bound) FP32 entries per centroid
         self.residual_table_bytes = residual_centroids * 64 * 4
@@ -84,7 +96,7 @@ class Scheduler:
         self._next_bid = 0
 
     def cost(self, r: Request) -> int:
-        c = request_bytes(len(r.query), len(r.cand_ids), self.dim, self.k)
+        c = request_bytes(len(r.query), len(r.cand_ids), self.dim, self.k, topk_ws=self.topk_ws)
         if r.mode == "residual":
             c += self.residual_table_bytes
         return c
@@ -167,6 +179,11 @@ class Backend:
         """Per request, (top ids int64 [k], top scores float32 [k])."""
         raise NotImplementedError
 
+    def release(self, handle):
+        """Gives back what a launched batch holds when it failed after its
+        launch (its poll or results raised): the server calls this instead of
+        results()."""
+
 
 class GpuBackend(Backend):
     """Launches a batch as one fused scoring call and one top-k call on a
@@ -208,7 +225,6 @@ class GpuBackend(Backend):
             sl["nreq"] = n
 
     def launch(self, batch: Batch):
-        torch, B = self.torch, self.B
         reqs = batch.requests
         sl = self._slot()
         s = sl["stream"]
@@ -231,7 +247,23 @@ class GpuBackend(Backend):
         np.cumsum(nc, out=c_off[1:])
         np.concatenate([r.query for r in reqs], out=h[o_tok:o_ids].view(np.float32).reshape(tq, dim))
         np.concatenate([r.cand_ids for r in reqs], out=h[o_ids:nbytes].view(np.int32))
-        d = sl["dev"]
+        try:
+            handle = self._enqueue(batch, sl, nq, tq, tc, n, dim, o_q, o_c, o_tok, o_ids, nbytes)
+        except BaseException:
+            # work may already be queued on the slot's stream (the copy out of
+            # its pinned buffer): let it drain before the slot is reused
+            try:
+                s.synchronize()
+            finally:
+                sl["busy"] = False
+            raise
+        return handle
+
+    def _enqueue(self, batch, sl, nq, tq, tc, n, dim, o_q, o_c, o_tok, o_ids, nbytes):
+        torch, B = self.torch, self.B
+        s, d = sl["stream"], sl["dev"]
+        # the slot is taken from the first enqueued operation on
+        sl["busy"] = True
         with torch.cuda.stream(s):
             d[:nbytes].copy_(sl["host"][:nbytes], non_blocking=True)
             qoff = d[o_q:o_c].view(torch.int64)
@@ -256,7 +288,6 @@ class GpuBackend(Backend):
             sl["out_i"][:n].copy_(ti, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        sl["busy"] = True
         # the device temporaries stay referenced until the event has completed
         return (ev, sl, n, (qt, scores, ts, ti))
 
@@ -265,11 +296,19 @@ class GpuBackend(Backend):
 
     def results(self, handle):
         ev, sl, n, _ = handle
-        ev.synchronize()
-        out_s, out_i = sl["out_s"].numpy(), sl["out_i"].numpy()
-        res = [(out_i[i].astype(np.int64), out_s[i].copy()) for i in range(n)]
-        sl["busy"] = False
-        return res
+        try:
+            ev.synchronize()
+            out_s, out_i = sl["out_s"].numpy(), sl["out_i"].numpy()
+            return [(out_i[i].astype(np.int64), out_s[i].copy()) for i in range(n)]
+        finally:
+            sl["busy"] = False
+
+    def release(self, handle):
+        _, sl, _, _ = handle
+        try:
+            sl["stream"].synchronize()
+        finally:
+            sl["busy"] = False
 
 
 class Server:
@@ -292,6 +331,12 @@ class Server:
     def _complete_batch(self, b: Batch, now: float):
         try:
             if isinstance(b.handle, _Failed):
+                if b.handle.handle is not None:
+                    # launched, then its poll raised: free what it holds
+                    try:
+                        self.backend.release(b.handle.handle)
+                    except Exception:  # noqa: BLE001 -- the batch fails either way
+                        pass
                 raise b.handle.e
             res = self.backend.results(b.handle)
             for r, (ids, sc) in zip(b.requests, res):
@@ -317,7 +362,7 @@ class Server:
                     ready = self.backend.poll(b.handle)
                 except Exception as e:  # noqa: BLE001
                     ready = True
-                    b.handle = _Failed(e)
+                    b.handle = _Failed(e, b.handle)
             if ready:
                 self._complete_batch(b, self.clock())
                 progressed = True
@@ -358,10 +403,11 @@ class Server:
 
 
 class _Failed:
-    """Handle of a batch whose launch or poll raised."""
+    """Handle of a batch whose launch or poll raised; `handle` is the
+    backend's handle when the launch itself had succeeded."""
 
-    def __init__(self, e):
-        self.e = e
+    def __init__(self, e, handle=None):
+        self.e, self.handle = e, handle
 
 
 def latency_stats(reqs: List[Request]) -> dict:

@@ -203,3 +203,87 @@ def test_residual_requests_are_charged_for_their_table_columns():
     tight = S.Scheduler(64, 10, mem_budget=base + 1000, residual_centroids=1000)
     r = S.Request(3, q, ids, mode="residual")
     assert not tight.submit(r) and r.status == "rejected"
+
+
+def test_request_charge_covers_the_library_topk_workspace():
+    # the memory admission charges at least the top-k workspace the library
+    # itself asks for per segment (maxsim_topk_workspace_size)
+    from paper_2606_26439_amd import _binding as B
+    for k in (1, 10, 100, 1024):
+        ws = B.topk_workspace_bytes(1, k)
+        assert ws > 0
+        assert S.request_bytes(1, 1, 64, k) >= ws + 8 * k
+        assert S.Scheduler(64, k).cost(S.Request(0, np.zeros((1, 64), np.float32),
+                                                 np.zeros(1, np.int32))) >= ws
+    # n segments need n times one segment's workspace
+    assert B.topk_workspace_bytes(7, 100) == 7 * B.topk_workspace_bytes(1, 100)
+
+
+class SlotBackend(FakeBackend):
+    """FakeBackend with GpuBackend's slot discipline: a fixed number of
+    execution slots, taken at launch and given back by results() or
+    release(); a launch without a free slot raises. `poll_fail` / `launch_fail`
+    name request ids whose poll / launch raises (once each)."""
+
+    def __init__(self, clock, pool, n_slots=1, poll_fail=(), launch_fail=(), **kw):
+        super().__init__(clock, pool, **kw)
+        self.free = n_slots
+        self.poll_fail, self.launch_fail = set(poll_fail), set(launch_fail)
+        self.released = 0
+
+    def launch(self, batch):
+        if self.free == 0:
+            raise RuntimeError("no free execution slot")
+        hit = self.launch_fail & {r.rid for r in batch.requests}
+        if hit:
+            self.launch_fail -= hit
+            raise RuntimeError("injected launch failure")  # nothing taken
+        self.free -= 1
+        return super().launch(batch)
+
+    def poll(self, h):
+        hit = self.poll_fail & {r.rid for r in h["batch"].requests}
+        if hit:
+            self.poll_fail -= hit
+            raise RuntimeError("injected poll failure")
+        return super().poll(h)
+
+    def results(self, h):
+        try:
+            return super().results(h)
+        finally:
+            self.free += 1
+
+    def release(self, h):
+        self._inflight -= 1
+        self.free += 1
+        self.released += 1
+
+
+@pytest.mark.parametrize("n_slots", [1, 2])
+def test_failed_poll_gives_its_slot_back(pool, n_slots):
+    # a batch whose poll raises fails its own requests; its slot returns, so
+    # every later batch still runs (with no release, all of them would fail
+    # with "no free execution slot")
+    reqs = make_requests(10, 300, rate=1e6)
+    clock = SimClock()
+    be = SlotBackend(clock, pool, n_slots=n_slots, poll_fail={2, 5}, per_pair=1e-4)
+    srv = S.Server(S.Scheduler(dim=64, k=10, max_inflight=n_slots, max_batch_requests=1), be,
+                   clock=clock, idle=clock.idle)
+    done = srv.run(reqs)
+    st = {r.rid: r.status for r in done}
+    assert st[2] == "error" and st[5] == "error"
+    assert all(st[i] == "done" for i in st if i not in (2, 5)), st
+    assert be.released == 2 and be.free == n_slots
+
+
+def test_failed_launch_leaves_no_slot_taken(pool):
+    reqs = make_requests(6, 300, rate=1e6)
+    clock = SimClock()
+    be = SlotBackend(clock, pool, n_slots=1, launch_fail={1}, per_pair=1e-4)
+    srv = S.Server(S.Scheduler(dim=64, k=10, max_inflight=1, max_batch_requests=1), be,
+                   clock=clock, idle=clock.idle)
+    done = srv.run(reqs)
+    st = {r.rid: r.status for r in done}
+    assert st[1] == "error" and all(st[i] == "done" for i in st if i != 1), st
+    assert be.free == 1 and be.released == 0
