@@ -175,6 +175,67 @@ def oracle_sample(wl, dtype, got_scores, n_sample, seed=5, n_o2=20000):
              "max": float(e2.max()), "n_docs": m})
 
 
+def oracle_threads():
+    """Threads for the all-core oracle: the cores this process may run on,
+    at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_all_cores(wl, dtype, gpu_scores, n_threads, chunk_docs=25_000):
+    """The FP64 oracle over EVERY document of the workload, sharded over
+    n_threads host threads (each runs the single-threaded C oracle on its own
+    document ranges; ctypes releases the interpreter lock). Untimed: the FP32
+    source rows are copied to the host and rounded by the oracle's own
+    conversion, chunk by chunk. Timed: the oracle's decode to FP64 and Eq. (1)
+    for all chunks. Returns docs/s, seconds, the max rel error of every GPU
+    score against it, and the oracle's exact top-100 ids."""
+    import torch
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    assert dtype == "f16"
+    offs = wl.d_off_np
+    bounds = list(range(0, wl.n_docs, chunk_docs)) + [wl.n_docs]
+    spans = list(zip(bounds[:-1], bounds[1:]))
+    qv, _ = oracle.exact_values(wl.q_np, dtype)
+
+    def fetch(span):
+        b0, b1 = span
+        x = wl.d_f32[int(offs[b0]):int(offs[b1])].cpu().numpy()
+        return oracle.round_f16(x)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(n_threads) as ex:
+        bits = list(ex.map(fetch, spans))
+    prep = time.perf_counter() - t0
+
+    def score(i):
+        b0, b1 = spans[i]
+        dv = oracle.decode_f16(bits[i])
+        return oracle.maxsim(qv, wl.q_off_np, dv, offs[b0:b1 + 1] - offs[b0])
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(n_threads) as ex:
+        parts = list(ex.map(score, range(len(spans))))
+    secs = time.perf_counter() - t0
+    del bits
+    exact = np.concatenate(parts)
+    got = gpu_scores.astype(np.float64)
+    rel = np.abs(got - exact) / np.maximum(np.abs(exact), 1.0)
+    top = np.lexsort((np.arange(wl.n_docs), -exact))[:100]
+    return {"value": wl.n_docs / secs, "unit": "docs/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"all {wl.n_docs} docs, FP64 single-threaded C per thread, "
+                      f"{len(spans)} ranges of {chunk_docs} docs over {n_threads} threads, "
+                      f"{secs:.1f}s (decode + Eq. (1); host copy and rounding {prep:.1f}s "
+                      f"untimed)",
+            "per_core_docs_per_s": wl.n_docs / secs / n_threads,
+            "gpu_vs_oracle_max_rel_err_all_docs": float(rel.max()),
+            "_exact_top100": top}
+
+
 def exact_topk(wl, f32_scores, k=100, margin=1e-3):
     """The FP64 oracle's top-k ids over all documents (on the FP32 source
     tokens), found without scoring every document on the CPU: a document
@@ -520,8 +581,46 @@ def bench_dim_tiling(batch_sizes=(100_000, 250_000, 500_000), dims=(64, 256, 512
     return out
 
 
+def _force_pq(variant, nqb=0, key=None):
+    """Makes maxsim_pq_score use one PQ scorer (tune-cache entries loaded into
+    the library) for one key (M, dsub, query blocks, candidates) or, with
+    key=None, every key. variant 1 with nqb 0 is the library's own default."""
+    import tempfile
+    import paper_2606_26439_amd as M
+    keys = [key] if key else [(m, ds, b, c) for m in (4, 8, 16) for ds in (8, 16, 32)
+                              for b in (1, 2, 4) for c in (0, 1)]
+    entries = [{"pq": 1, "M": m, "dsub": ds, "bpq": b, "cand": c, "variant": variant, "nqb": nqb}
+               for m, ds, b, c in keys]
+    with tempfile.NamedTemporaryFile("w", suffix=".json", delete=False) as f:
+        json.dump({"version": 1, "entries": entries}, f)
+    M.load_tune_cache(f.name)
+    os.unlink(f.name)
+
+
+def lds_ceilings(buf):
+    """Measured LDS read ceilings (maxsim_lds_probe over `buf`, 128 KiB table):
+    lane-level reads per second and bytes per second for random 4-byte reads,
+    random 16-byte reads and conflict-free 16-byte reads."""
+    import paper_2606_26439_amd as M
+    from paper_2606_26439_amd import _binding as B
+    out = {}
+    for v, name in ((0, "random_4B"), (1, "random_16B"), (2, "conflict_free_16B")):
+        med, _, _ = time_fn(lambda: M.lds_probe(buf, v), 10, 3)
+        reads = buf.numel() * buf.element_size() / 16 * B.LDS_PROBE_READS_PER_16B[v]
+        out[name] = {"reads_per_s": reads / (med * 1e-3),
+                     "TBps": reads * B.LDS_PROBE_READ_BYTES[v] / (med * 1e-3) / 1e12,
+                     "ms": med}
+    return out
+
+
 def bench_pq(n_docs=2_000_000, n_queries=64, nq=32, M_=8, K=256, dsub=16):
-    """64 queries x 32 tokens against 2M PQ-coded docs in one launch."""
+    """64 queries x 32 tokens against 2M PQ-coded docs in one launch. Both
+    scorers are timed on the headline protocol (5 warm-up, 10 timed launches):
+    the table kernel (Sec. 4.3: table in LDS, one 16-byte read per four query
+    tokens per subspace) against the measured conflict-free LDS read ceiling,
+    the decode-into-MFMA kernel (codebooks in LDS, one random 16-byte read per
+    lane per k-step) against the FP16 matrix peak and the measured random
+    16-byte LDS read ceiling."""
     import torch
     import oracle
     import paper_2606_26439_amd as M
@@ -539,10 +638,50 @@ def bench_pq(n_docs=2_000_000, n_queries=64, nq=32, M_=8, K=256, dsub=16):
     D = M.PQDocs(torch.from_numpy(cb_np).cuda(), codes, torch.from_numpy(d_off_np).cuda())
     n_pairs = n_queries * n_docs
     sc = torch.empty(n_pairs, dtype=torch.float32, device="cuda")
-    # both PQ scorers timed on this problem; the faster stays selected
+    # both PQ scorers (and the decode kernel's query-block counts) timed on
+    # this problem; the faster becomes the scorer this section reports first
     tune = M.pq_autotune(Q, D, reps=2)
-    log(f"[bench] PQ M={M_} dsub={dsub} scorers: {tune['trials']}")
-    med, mean, std = time_fn(lambda: M.pq_score(Q, D, out=sc), 3, 1)
+    log(f"[bench] PQ M={M_} dsub={dsub} scorer trials: {tune['trials']}")
+    best = tune["best"]
+    kern = {}
+    bpq = (nq + 15) // 16
+    nks = M_ * dsub // 32
+    for variant in (best["variant"], 1 - best["variant"]):
+        if variant == 1:
+            nqb = best["nqb"] if best["variant"] == 1 else max(
+                (t for t in tune["trials"] if t["variant"] == 1), key=lambda t: -t["ms"])["nqb"]
+            _force_pq(1, nqb)
+        else:
+            _force_pq(0)
+        med, mean, std = time_fn(lambda: M.pq_score(Q, D, out=sc), 10, 5)
+        if variant == 0:
+            # one ds_read_b128 per (query, quad of query tokens, subspace, doc token)
+            reads = n_queries * (nq // 4) * M_ * T
+            kern["table"] = {"ms_median": med, "ms_mean": mean, "ms_std": std,
+                             "lds_16B_reads_per_s": reads / (med * 1e-3),
+                             "table_entries_per_s": n_queries * nq * M_ * T / (med * 1e-3)}
+        else:
+            # per 16-row tile and k-step, each lane reads 16 bytes of one
+            # centroid: 4 * nks reads per document token per query group
+            groups = n_queries // max(1, nqb // bpq)
+            reads = groups * T * 4 * nks
+            fl = 2.0 * n_queries * nq * M_ * dsub * T
+            kern["decode_mfma"] = {"ms_median": med, "ms_mean": mean, "ms_std": std, "nqb": nqb,
+                                   "lds_16B_reads_per_s": reads / (med * 1e-3),
+                                   "mfma_f16_tflops_algorithmic": fl / (med * 1e-3) / 1e12,
+                                   "mfma_f16_frac": fl / (med * 1e-3) / R.PEAK_FLOPS["f16"]}
+        if variant == best["variant"]:
+            M.pq_score(Q, D, out=sc)  # the reported scores come from the faster scorer
+            got_all = sc.view(n_queries, n_docs).clone()
+    # back to the default for every key, and the tuned choice for this one
+    _force_pq(1, 0)
+    _force_pq(best["variant"], best["nqb"], key=(M_, dsub, 1 << (bpq - 1).bit_length(), 0))
+    ceil = lds_ceilings(codes)
+    kern["table"]["frac_of_conflict_free_lds_ceiling"] = (
+        kern["table"]["lds_16B_reads_per_s"] / ceil["conflict_free_16B"]["reads_per_s"])
+    kern["decode_mfma"]["frac_of_random_16B_lds_ceiling"] = (
+        kern["decode_mfma"]["lds_16B_reads_per_s"] / ceil["random_16B"]["reads_per_s"])
+    med = kern["decode_mfma" if best["variant"] == 1 else "table"]["ms_median"]
     # sampled check: 3 queries x 300 docs, decode-then-score in FP64
     g = np.random.default_rng(13)
     docs = np.sort(g.choice(n_docs, size=300, replace=False))
@@ -550,33 +689,32 @@ def bench_pq(n_docs=2_000_000, n_queries=64, nq=32, M_=8, K=256, dsub=16):
     codes_s = codes[torch.from_numpy(rows).cuda()].cpu().numpy()
     s_off = W.offsets_from_lengths(lens[docs])
     qv, _ = oracle.exact_values(q, "f16")
-    got_all = sc.view(n_queries, n_docs)
     worst = 0.0
     for a in (0, 31, 63):
         want = oracle.pq_decode_score(qv[a * nq:(a + 1) * nq], [0, nq], codes_s,
                                       cb_np.astype(np.float64), s_off)
         got = got_all[a, torch.from_numpy(docs).cuda()].cpu().numpy().astype(np.float64)
         worst = max(worst, float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1.0))))
-    gathers = n_queries * nq * M_ * T
-    lds_peak_gathers = 256 * 2.4e9 * 128 / 4  # 128 B/clk/CU of 4-byte words
     hb = R.pq_bytes(T, n_docs, n_queries, M_)
     rec = {"ms_median": med, "n_docs": n_docs, "n_doc_tokens": T, "n_queries": n_queries,
            "nq": nq, "M": M_, "K": K, "dsub": dsub,
            "pairs_per_s": n_pairs / (med * 1e-3),
-           "docs_per_s_per_query": n_docs / (med * 1e-3) * n_queries / n_queries,
+           "docs_per_s_per_query": n_docs / (med * 1e-3),
            "query_doc_pairs_per_s": n_pairs / (med * 1e-3),
-           "lds_gathers_per_s": gathers / (med * 1e-3),
-           "lds_gather_frac": gathers / (med * 1e-3) / lds_peak_gathers,
            "hbm_frac_of_codes_once": hb / (med * 1e-3) / HBM_PEAK,
            "sampled_max_rel_err_vs_decode_then_score": worst,
-           "scorer": "decode-into-MFMA" if tune["best"]["variant"] == 1 else "table in LDS",
-           "scorer_trials_ms": tune["trials"]}
-    if tune["best"]["variant"] == 1:
-        fl = 2.0 * n_queries * nq * M_ * dsub * T
-        rec["mfma_f16_frac_unpadded"] = fl / (med * 1e-3) / R.PEAK_FLOPS["f16"]
-    log(f"[bench] PQ M={M_} dsub={dsub}: {med:.2f} ms, {rec['pairs_per_s'] / 1e9:.2f} G pairs/s, "
-        f"LDS gather frac {rec['lds_gather_frac'] * 100:.1f}%, err {worst:.1e}")
-    del codes, sc
+           "scorer": "decode-into-MFMA" if best["variant"] == 1 else "table in LDS",
+           "scorer_trials_ms": tune["trials"], "kernels": kern,
+           "measured_lds_ceilings": ceil}
+    dk, tk = kern["decode_mfma"], kern["table"]
+    rec["summary"] = (f"{med:.2f} ms ({rec['scorer']}), {rec['pairs_per_s'] / 1e9:.2f} G pairs/s; "
+                      f"decode-into-MFMA {dk['ms_median']:.2f} ms = {dk['mfma_f16_frac'] * 100:.1f}% "
+                      f"of FP16 MFMA peak, LDS {dk['frac_of_random_16B_lds_ceiling'] * 100:.1f}% of "
+                      f"random 16-B ceiling; table {tk['ms_median']:.1f} ms = "
+                      f"{tk['frac_of_conflict_free_lds_ceiling'] * 100:.1f}% of conflict-free LDS "
+                      f"ceiling; err {worst:.1e}")
+    log(f"[bench] PQ M={M_} dsub={dsub}: {rec['summary']}")
+    del codes, sc, got_all
     torch.cuda.empty_cache()
     return rec
 
@@ -954,6 +1092,7 @@ def main():
         del cal
         log(f"[bench] calibration copy: {n_cal * wl.dim * 4} bytes read and written")
 
+    summary = []
     if not args.profile:
         got = scores.cpu().numpy()
         dps, secs, relmax, o2 = oracle_sample(wl, "f16", got, args.cpu_sample)
@@ -962,6 +1101,19 @@ def main():
                                          f"single-threaded C, {secs:.1f}s",
                                "gpu_vs_oracle_max_rel_err": relmax, "f16_vs_fp32_abs_err": o2}
         log(f"[bench] oracle {dps:.0f} docs/s on 1 core; sampled max rel err {relmax:.2e}")
+        if not args.quick and "allcores" not in set(args.skip.split(",")):
+            allc = oracle_all_cores(wl, "f16", got, oracle_threads())
+            ex_top = set(allc.pop("_exact_top100").tolist())
+            gpu_top = set(M.topk(scores, seg, 100, workspace=tk_ws)[1].cpu().numpy()[0].tolist())
+            allc["gpu_top100_overlap_with_oracle_top100"] = len(gpu_top & ex_top)
+            out["cpu_baseline"]["all_cores"] = allc
+            summary.append(
+                f"oracle on {allc['cores']} cores: all {wl.n_docs} docs in "
+                f"{wl.n_docs / allc['value']:.1f}s ({allc['value']:.0f} docs/s; 1 core "
+                f"{dps:.0f}); every GPU score within {allc['gpu_vs_oracle_max_rel_err_all_docs']:.1e}"
+                f" rel; GPU top-100 vs oracle top-100 {allc['gpu_top100_overlap_with_oracle_top100']}"
+                f"/100")
+            log("[bench] " + summary[-1])
 
     skip = set(x for x in args.skip.split(",") if x)
     if not args.quick and not args.profile and "forms" not in skip:
@@ -989,11 +1141,16 @@ def main():
             if dt == "f32":
                 fl = R.flops(1, wl.nq, wl.T, wl.dim)
                 forms[dt]["mfma_f32_frac"] = fl / (med * 1e-3) / R.PEAK_FLOPS["f32"]
-            log(f"[bench] {dt}: {med:.3f} ms, {forms[dt]['hbm_frac'] * 100:.1f}% HBM")
+            log(f"[bench] {dt}: {med:.3f} ms, {forms[dt]['hbm_frac'] * 100:.1f}% HBM, top-100 "
+                f"vs f16 {forms[dt]['top100_overlap_with_f16']}/100, vs FP64 oracle "
+                f"{forms[dt]['top100_overlap_with_fp64_oracle']}/100")
             if dt != "f16":
                 del wl.forms[dt]
                 torch.cuda.empty_cache()
         out["forms"] = forms
+        summary.append("forms (ms, % of 8 TB/s, top-100 vs FP64 oracle): " + "; ".join(
+            f"{dt} {f['ms_median']:.3f} {f['hbm_frac'] * 100:.1f}% "
+            f"{f['top100_overlap_with_fp64_oracle']}/100" for dt, f in forms.items()))
 
     if not args.quick and not args.profile and "plain" not in skip:
         out["plain_fp32"] = bench_plain_fp32()
@@ -1017,7 +1174,13 @@ def main():
                           "hbm_frac_of_its_bytes": bu / (med * 1e-3) / HBM_PEAK,
                           "alg_bytes": bu, "top100_identical_to_fused": top_u == top_f16,
                           "fused_ms_median": fused_med, "fused_speedup": med / fused_med}
-        log(f"[bench] unfused: {med:.3f} ms ({med / fused_med:.2f}x fused)")
+        log(f"[bench] unfused: {med:.3f} ms ({med / fused_med:.2f}x fused), "
+            f"top-100 identical {out['unfused']['top100_identical_to_fused']}")
+        summary.append(
+            f"unfused comparator {med:.3f} ms ({out['unfused']['hbm_frac_of_its_bytes'] * 100:.1f}%"
+            f" of 8 TB/s on its {bu / 1e9:.1f} GB) vs fused {fused_med:.3f} ms: "
+            f"{med / fused_med:.2f}x (byte ratio {bu / wl.alg_bytes('f16'):.2f}x); "
+            f"top-100 identical {out['unfused']['top100_identical_to_fused']}")
         del ws, su
         torch.cuda.empty_cache()
 
@@ -1057,6 +1220,14 @@ def main():
             "B=500K": {"docs_per_s": batch[500_000]["docs_per_s"],
                        "ms": batch[500_000]["ms_median"]}}
     out["paper_context"] = ctx
+    summary.insert(0, f"headline: fused f16 {out['roofline']['launch_ms_mean']:.3f} ms/launch "
+                      f"({out['roofline']['frac'] * 100:.1f}% of 8 TB/s), step "
+                      f"{ms_per_step:.3f} ms, {value / 1e6:.0f}M docs/s")
+    for k_, r_ in (("pq", out.get("pq")), ("pq_paper_shape", out.get("pq_paper_shape"))):
+        if r_:
+            summary.append(f"{k_}: {r_['summary']}")
+    for line in summary:
+        log("[bench] summary: " + line)
     print(json.dumps(out), flush=True)
 
 

@@ -67,7 +67,9 @@ typedef enum {
  * A CSR set of token-vector sets (documents or queries). Q in R^{Nq x d} and
  * D in R^{Nd x d} of Eq. (1), one set each.
  *   dtype     element type of `tokens`.
- *   dim       d; a multiple of 64, 64 <= dim <= 1024.
+ *   dim       d; a multiple of 16, 16 <= dim <= 1024 (the kernels work in
+ *             d-chunks of 64, 128 or 256 and zero-extend the last chunk, which
+ *             adds exact zeros: the scores equal those of the zero-padded rows).
  *   n_sets    number of sets; n_tokens = offsets[n_sets] (host copies, so the
  *             library needs no device-to-host read).
  *   max_len   host upper bound on tokens per set. For queries it selects the
@@ -164,6 +166,7 @@ const char* maxsim_last_error(void);
  *           max_u |x_u| <= 448 * 2^k (s = 1 for an all-zero token), written to
  *           scales[t]; codes = E4M3FN(x / s), round to nearest even.
  *   F32: plain copy.
+ * dim: a multiple of 16, 16 <= dim <= 1024 (else MAXSIM_EUNSUPPORTED).
  * dst has n_tokens * dim elements of `dtype`.
  */
 maxsim_status maxsim_quantize(const float* src, int64_t n_tokens, int32_t dim, int32_t dtype,
@@ -367,6 +370,26 @@ maxsim_status maxsim_check(const int32_t* flags, maxsim_stream_t stream);
  */
 maxsim_status maxsim_stream_probe(const void* buf, size_t bytes, int32_t variant, uint32_t* sink,
                                   int64_t sink_len, maxsim_stream_t stream);
+
+/*
+ * Measured LDS gather ceiling, the bound of the PQ scorers: the table kernel
+ * gathers lookup-table entries from LDS (Sec. 4.3 Phase 2) and the
+ * decode-into-MFMA kernel gathers codebook rows (the ADC identity, Sec. 4.2).
+ * One workgroup of 16 waves per CU (grid min(sink_len / 16, CUs)) fills a
+ * table of table_bytes (65536 or 131072) in LDS, then streams `bytes` of
+ * buf (16-byte aligned; whole 1 KiB units, non-temporal) and turns every
+ * 4-byte word into 8 table indices, each read by one LDS instruction:
+ *   variant 0: random 4-byte reads, 4 passes per word (128 reads per lane per
+ *              16 bytes streamed);
+ *   variant 1: random 16-byte reads (32 per lane per 16 bytes);
+ *   variant 2: 16-byte reads whose 16 lanes per quarter-wave hit 16 distinct
+ *              16-byte bank groups (conflict-free; 32 per lane per 16 bytes).
+ * Writes one XOR checksum per wave to sink (sink_len >= 16). Time it with
+ * events: reads = bytes / 16 * (variant 0 ? 128 : 32).
+ */
+maxsim_status maxsim_lds_probe(const void* buf, size_t bytes, int32_t variant,
+                               int32_t table_bytes, uint32_t* sink, int64_t sink_len,
+                               maxsim_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -107,9 +107,12 @@ def lib():
     L.maxsim_load_tune_cache.argtypes = [ctypes.c_char_p]
     L.maxsim_stream_probe.argtypes = [_vp, ctypes.c_size_t, ctypes.c_int32, _vp, ctypes.c_int64,
                                       _vp]
+    L.maxsim_lds_probe.argtypes = [_vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _vp,
+                                   ctypes.c_int64, _vp]
     for name in ("maxsim_quantize", "maxsim_score", "maxsim_score_unfused", "maxsim_pq_score",
                  "maxsim_topk", "maxsim_autotune", "maxsim_pq_autotune",
-                 "maxsim_load_tune_cache", "maxsim_stream_probe", "maxsim_validate",
+                 "maxsim_load_tune_cache", "maxsim_stream_probe", "maxsim_lds_probe",
+                 "maxsim_validate",
                  "maxsim_validate_pq", "maxsim_check", "maxsim_residual_score",
                  "maxsim_validate_residual", "maxsim_residual_autotune"):
         getattr(L, name).restype = ctypes.c_int
@@ -407,6 +410,20 @@ def stream_probe(buf, variant: int = 0, stream=None):
     sink = torch.empty(256 * 8 * 4, dtype=torch.int32, device=buf.device)
     _check(lib().maxsim_stream_probe(_ptr(buf), buf.numel() * buf.element_size(), variant,
                                      _ptr(sink), sink.numel(), _stream(stream)))
+    return sink
+
+
+LDS_PROBE_READS_PER_16B = {0: 128, 1: 32, 2: 32}
+LDS_PROBE_READ_BYTES = {0: 4, 1: 16, 2: 16}
+
+
+def lds_probe(buf, variant: int = 1, table_bytes: int = 131072, stream=None):
+    """Streams the bytes of `buf` and gathers from an LDS table for each word
+    (maxsim_lds_probe); returns the checksum tensor. Lane-level reads issued:
+    buf bytes / 16 * LDS_PROBE_READS_PER_16B[variant]."""
+    sink = torch.empty(256 * 16, dtype=torch.int32, device=buf.device)
+    _check(lib().maxsim_lds_probe(_ptr(buf), buf.numel() * buf.element_size(), variant,
+                                  table_bytes, _ptr(sink), sink.numel(), _stream(stream)))
     return sink
 
 

@@ -47,6 +47,25 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
 
 
+def _deps(src):
+    """Files an object depends on: its source and the headers it can include
+    (the fused scorer's implementation header only for its own unit)."""
+    hdrs = [os.path.join(CSRC, h) for h in ("device_common.h", "kernels.h")]
+    hdrs.append(os.path.join(HERE, "..", "include", "maxsim.h"))
+    if src == "fused_inst.hip":
+        hdrs.append(os.path.join(CSRC, "fused_impl.h"))
+    return [os.path.join(CSRC, src)] + hdrs + [os.path.abspath(__file__)]
+
+
+def _stale(spec) -> bool:
+    src, name, _ = spec
+    obj = os.path.join(BUILD_DIR, name + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in _deps(src))
+
+
 def _compile(spec) -> str:
     src, name, extra = spec
     obj = os.path.join(BUILD_DIR, name + ".o")
@@ -57,11 +76,15 @@ def _compile(spec) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, only_changed: bool = False) -> str:
+    """Compiles every source (only_changed: only objects older than their
+    source or headers) and links the library."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    workers = min(len(SOURCES), max(1, min(8, os.cpu_count() or 4)))
+    todo = [sp for sp in SOURCES if not only_changed or _stale(sp)]
+    workers = min(max(1, len(todo)), max(1, min(8, os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(workers) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD_DIR, name + ".o") for _, name, _ in SOURCES]
     tmp = OUT + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -74,5 +97,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, only_changed="--changed" in sys.argv[1:])
     sys.exit(0)

@@ -43,8 +43,8 @@ maxsim_status check_csr(const maxsim_csr* c, const char* name, bool is_query) {
   if (!c) return fail(MAXSIM_EINVAL, "%s: descriptor is NULL", name);
   if (c->dtype < MAXSIM_F32 || c->dtype > MAXSIM_F8E4M3)
     return fail(MAXSIM_EINVAL, "%s: unknown dtype %d", name, c->dtype);
-  if (c->dim < 64 || c->dim > 1024 || c->dim % 64 != 0)
-    return fail(MAXSIM_EUNSUPPORTED, "%s: dim %d must be a multiple of 64 in [64, 1024]", name,
+  if (c->dim < 16 || c->dim > 1024 || c->dim % 16 != 0)
+    return fail(MAXSIM_EUNSUPPORTED, "%s: dim %d must be a multiple of 16 in [16, 1024]", name,
                 c->dim);
   if (c->n_sets < 0 || c->n_tokens < 0)
     return fail(MAXSIM_EINVAL, "%s: negative n_sets or n_tokens", name);
@@ -194,30 +194,39 @@ maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_
   }
   if (n_pairs > 0 && !scores) return fail(MAXSIM_EINVAL, "scores is NULL");
   pl.dt = q->dtype;
-  // d-chunk width: 128 (the paper's dimension tiling), 64 when d is not a
-  // multiple of 128, and 256 for 1- and 2-byte rows of d >= 512 (same k
-  // order, so the same bits; each row read becomes 512 contiguous bytes)
-  pl.dch = (q->dim % 128 == 0) ? 128 : 64;
+  // d-chunk width: 128 (the paper's dimension tiling), 64 when d > 128 is not
+  // a multiple of 128, and 256 for 1- and 2-byte rows of d >= 512 (same k
+  // order, so the same bits; each row read becomes 512 contiguous bytes). A d
+  // that is not a multiple of the chunk is zero-extended to whole chunks
+  // inside the kernel: the query operand's columns past d are zero and the
+  // document columns past d are read from inside the row, so they add exact
+  // zeros. d <= 128 takes one chunk (64 wide up to 64, else 128).
+  if (q->dim <= 128)
+    pl.dch = q->dim <= 64 ? 64 : 128;
+  else
+    pl.dch = (q->dim % 128 == 0) ? 128 : 64;
   if (esize(q->dtype) <= 2 && q->dim >= 512 && q->dim % 256 == 0) pl.dch = 256;
-  const int nch = q->dim / pl.dch;
+  const int nch = (q->dim + pl.dch - 1) / pl.dch;
   pl.qreg = nch == 1;
   // Query units: without candidate lists, queries are grouped so one read of
   // a document tile serves several of them (up to 8 blocks of 16 query tokens
   // in VGPRs for 1- and 2-byte types, 4 otherwise).
   const int bpq = nqb_for(q->max_len);
   const int row_bytes = q->dim * esize(q->dtype);
+  // the query operand's row in LDS spans whole chunks
+  const int qrow_bytes = nch * pl.dch * esize(q->dtype);
   int group = 1;
   if (!cand && group_queries) {
     // in LDS (d beyond one chunk) the grouped query blocks leave at least
     // half of it to the staging ring
     const int cap = (pl.qreg && esize(q->dtype) <= 2) ? 8 : 4;
     auto fits = [&](int gr) {
-      return pl.qreg || (size_t)gr * bpq * 16 * row_bytes <= device_info().max_lds / 2;
+      return pl.qreg || (size_t)gr * bpq * 16 * qrow_bytes <= device_info().max_lds / 2;
     };
     while (group * 2 * bpq <= cap && group * 2 <= q->n_sets && fits(group * 2)) group *= 2;
   }
   pl.nqb = group * bpq;
-  pl.lds = (size_t)pl.nqb * 16 * row_bytes;
+  pl.lds = (size_t)pl.nqb * 16 * qrow_bytes;
   if (pl.lds > device_info().max_lds)
     return fail(MAXSIM_EUNSUPPORTED, "query block of %zu bytes exceeds LDS", pl.lds);
   FusedParams& P = pl.P;
@@ -237,6 +246,7 @@ maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_
   P.dim = q->dim;
   P.nch = nch;
   P.row_bytes = row_bytes;
+  P.ncg = qrow_bytes / 64;
   P.group = group;
   P.bpq = bpq;
   P.n_units = (q->n_sets + group - 1) / group;
@@ -254,7 +264,7 @@ maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s)
   int dch = pl.dch;
   if (dch == 256 && (!cfg.stage || pl.lds + (size_t)cfg.nw * cfg.pf * 16 * 256 * esize(pl.dt) >
                                        di.max_lds)) {
-    dch = 128;
+    dch = 128;  // d is a multiple of 256 here: the same padded row
     P.nch = P.dim / dch;
   }
   // 32-row steps only where they exist (FP8, staged, one chunk)
@@ -350,8 +360,8 @@ const char* maxsim_last_error(void) { return g_err.c_str(); }
 maxsim_status maxsim_quantize(const float* src, int64_t n_tokens, int32_t dim, int32_t dtype,
                               void* dst, float* scales, maxsim_stream_t stream) {
   if (n_tokens < 0) return fail(MAXSIM_EINVAL, "quantize: negative n_tokens");
-  if (dim < 64 || dim > 1024 || dim % 64 != 0)
-    return fail(MAXSIM_EUNSUPPORTED, "quantize: dim %d must be a multiple of 64 in [64, 1024]", dim);
+  if (dim < 16 || dim > 1024 || dim % 16 != 0)
+    return fail(MAXSIM_EUNSUPPORTED, "quantize: dim %d must be a multiple of 16 in [16, 1024]", dim);
   if (dtype < MAXSIM_F32 || dtype > MAXSIM_F8E4M3)
     return fail(MAXSIM_EINVAL, "quantize: unknown dtype %d", dtype);
   if (n_tokens == 0) return MAXSIM_OK;
@@ -399,7 +409,7 @@ maxsim_status maxsim_score_unfused(const maxsim_csr* queries, const maxsim_csr* 
   FusedPlan pl;
   maxsim_status st = plan_fused(queries, docs, nullptr, scores, pl, /*group_queries=*/false);
   if (st) return st;
-  if (pl.dch == 256) {  // the comparator's tiles are 128 wide at most
+  if (pl.dch == 256) {  // the comparator's tiles are 128 wide at most (d % 256 == 0 here)
     pl.dch = 128;
     pl.P.nch = queries->dim / 128;
   }
@@ -1025,6 +1035,24 @@ maxsim_status maxsim_stream_probe(const void* buf, size_t bytes, int32_t variant
   int64_t grid = std::min<int64_t>(sink_len / 4, (int64_t)device_info().cus * 8);
   hipError_t e = launch_stream_probe(buf, bytes, variant, sink, (int)grid, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "stream_probe launch");
+  return MAXSIM_OK;
+}
+
+maxsim_status maxsim_lds_probe(const void* buf, size_t bytes, int32_t variant,
+                               int32_t table_bytes, uint32_t* sink, int64_t sink_len,
+                               maxsim_stream_t stream) {
+  if (!buf || !sink) return fail(MAXSIM_EINVAL, "lds_probe: NULL buffer");
+  if (!aligned(buf, 16)) return fail(MAXSIM_EINVAL, "lds_probe: buffer must be 16-byte aligned");
+  if (variant < 0 || variant > 2) return fail(MAXSIM_EINVAL, "lds_probe: variant must be in [0, 2]");
+  if (table_bytes != 65536 && table_bytes != 131072)
+    return fail(MAXSIM_EINVAL, "lds_probe: table_bytes must be 65536 or 131072");
+  if ((size_t)table_bytes > device_info().max_lds)
+    return fail(MAXSIM_EUNSUPPORTED, "lds_probe: table exceeds the LDS");
+  if (sink_len < 16) return fail(MAXSIM_EINVAL, "lds_probe: sink needs at least 16 entries");
+  const int64_t grid = std::min<int64_t>(sink_len / 16, (int64_t)device_info().cus);
+  hipError_t e =
+      launch_lds_probe(buf, bytes, variant, table_bytes, sink, (int)grid, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "lds_probe launch");
   return MAXSIM_OK;
 }
 

@@ -126,10 +126,10 @@ __device__ __forceinline__ int64_t unit_query(const FusedParams& P, int64_t u, i
 
 // Stage the NQB query blocks of unit u into LDS in the B-operand layout,
 // threads t0, t0 + nthreads, ... of the caller's group doing the copy; rows
-// past a query's end are zero.
+// past a query's end and columns past d (up to the whole last chunk) are zero.
 template <int NQB>
 __device__ void stage_unit(const FusedParams& P, int64_t u, u32x4* q_lds, int t0, int nthreads) {
-  const int ncg = P.row_bytes / 64;  // 16-byte column groups per lane-group row
+  const int ncg = P.ncg;  // 64-byte column groups of the chunk-padded row
   const int total = NQB * ncg * 64;
   for (int idx = t0; idx < total; idx += nthreads) {
     int ln = idx & 63, rest = idx >> 6;
@@ -141,7 +141,8 @@ __device__ void stage_unit(const FusedParams& P, int64_t u, u32x4* q_lds, int t0
       const int nq = (int)(P.q_off[qa + 1] - q0);
       const int row = (nb % P.bpq) * 16 + (ln & 15);
       const int beta = cg * 4 + (ln >> 4);
-      if (row < nq) v = *(const u32x4*)(P.q_tok + (q0 + row) * P.row_bytes + beta * 16);
+      if (row < nq && beta * 16 < P.row_bytes)
+        v = *(const u32x4*)(P.q_tok + (q0 + row) * P.row_bytes + beta * 16);
     }
     q_lds[idx] = v;
   }
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
   const int r = lane & 15, g = lane >> 4;
   const int wave = uniform(threadIdx.x >> 6);
   const int nch = P.nch;
-  const int ncg = P.row_bytes / 64;
+  const int ncg = P.ncg;
 
   const int64_t W = (int64_t)gridDim.x * NW;
   const int64_t wg0 = (int64_t)blockIdx.x * NW;
@@ -277,8 +278,8 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
         const char* qrow = P.q_tok + (q0 + row) * P.row_bytes + g * 16;
 #pragma unroll
         for (int c = 0; c < NL; ++c) {
-          u32x4 v = {0u, 0u, 0u, 0u};
-          if (row < nq) v = *(const u32x4*)(qrow + c * 64);
+          u32x4 v = {0u, 0u, 0u, 0u};  // zero past the query's end and past d
+          if (row < nq && c * 64 + g * 16 < P.row_bytes) v = *(const u32x4*)(qrow + c * 64);
           qreg[nb][c] = v;
         }
       }
@@ -343,16 +344,21 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     int flags[PF];
     int64_t fp[PF];
     constexpr int Q_COPIES = QM == Q_SHARED ? 1 : (QM == Q_WAVE ? NW : 0);
-    char* ring = (char*)q_lds + (size_t)Q_COPIES * NQB * 16 * P.row_bytes + (size_t)wave * PF * TILE;
+    char* ring =
+        (char*)q_lds + (size_t)Q_COPIES * NQB * 16 * ncg * 64 + (size_t)wave * PF * TILE;
     auto swz = [](int row) { return (row / SWD) & (SW - 1); };
 
     // Every fill issues exactly NL (+1 for FP8) loads, from a harmless address
     // when there is nothing left to load, so the compiler's vmcnt accounting
-    // sees a fixed depth of PF steps in flight.
+    // sees a fixed depth of PF steps in flight. Columns of the last chunk past
+    // d are read from the row's last 16 bytes instead (inside the row; the
+    // query operand is zero there, so they add exact zeros).
     auto fill = [&](const int s) {
       int f = 0;
       const char* base = g_zero_row;
       const bool live = cp < hi && cnd != 0;
+      // largest in-row offset from this step's chunk start (idle: none needed)
+      const int cmax = live ? P.row_bytes - 16 - cchunk * CB : CB;
       fp[s] = cp;
       if (cp < hi) {
         if (cnd == 0) {
@@ -360,7 +366,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
         } else {
           int row = ctile * RT + r;
           row = row < cnd ? row : cnd - 1;
-          base = P.d_tok + (ct0 + row) * P.row_bytes + cchunk * CB + g * 16;
+          base = P.d_tok + (ct0 + row) * P.row_bytes + cchunk * CB;
           f = F_VALID | (cchunk == 0 ? F_TFIRST : 0) | (cchunk << 8);
           if (cchunk == nch - 1) {
             f |= F_TLAST;
@@ -382,15 +388,19 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
         for (int w = 0; w < NLS; ++w) {
           const int ch = 64 * w + lane;  // LDS slot of this lane's 16 bytes
           const int rho = ch / CPR, p = ch % CPR;
+          const int col = (p ^ swz(rho)) * 16;
           const unsigned off =
-              (unsigned)((rho < lim ? rho : lim) * P.row_bytes + (p ^ swz(rho)) * 16);
+              (unsigned)((rho < lim ? rho : lim) * P.row_bytes + (col < cmax ? col : cmax));
           __builtin_amdgcn_global_load_lds((const void*)(tb + off),
                                            (__attribute__((address_space(3))) void*)(slot + w * 1024),
                                            16, 0, 2 /* non-temporal */);
         }
       } else {
 #pragma unroll
-        for (int c = 0; c < NL; ++c) buf[s][c] = *(const u32x4*)(base + c * 64);
+        for (int c = 0; c < NL; ++c) {
+          const int col = c * 64 + g * 16;
+          buf[s][c] = *(const u32x4*)(base + (col < cmax ? col : cmax));
+        }
       }
 #pragma unroll
       for (int h = 0; h < SUB; ++h) {
@@ -615,7 +625,7 @@ __global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, floa
   const int64_t a = blockIdx.y;
   const int64_t T = P.tokens_per_query;
   const int64_t ntiles = (T + 15) / 16;
-  const int ncg = P.row_bytes / 64;
+  const int ncg = P.ncg;
 
   stage_unit<NQB>(P, a, q_lds, threadIdx.x, NW * 64);  // group 1: unit a = query a
   const int nq = uniform((int)(P.q_off[a + 1] - P.q_off[a]));
@@ -641,9 +651,14 @@ __global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, floa
     for (int nb = 0; nb < NQB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int chunk = 0; chunk < P.nch; ++chunk) {
       u32x4 bb[NL];
-      const char* base = P.d_tok + row * P.row_bytes + chunk * CB + g * 16;
+      // columns past d: the row's last 16 bytes (the query operand is zero there)
+      const char* base = P.d_tok + row * P.row_bytes + chunk * CB;
+      const int cmax = P.row_bytes - 16 - chunk * CB;
 #pragma unroll
-      for (int c = 0; c < NL; ++c) bb[c] = *(const u32x4*)(base + c * 64);
+      for (int c = 0; c < NL; ++c) {
+        const int col = c * 64 + g * 16;
+        bb[c] = *(const u32x4*)(base + (col < cmax ? col : cmax));
+      }
 #pragma unroll
       for (int nb = 0; nb < NQB; ++nb) {
         u32x4 qb[NL];

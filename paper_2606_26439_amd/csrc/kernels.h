@@ -22,15 +22,17 @@ struct FusedParams {
   int64_t n_pairs;           // number of (query, doc) scores
   int64_t tokens_per_query;  // d_off[n_docs] (host copy)
   int32_t dim;
-  int32_t nch;        // dim / DCH
-  int32_t row_bytes;  // dim * element size
+  int32_t nch;        // ceil(dim / DCH): d-chunks per row
+  int32_t row_bytes;  // dim * element size (row stride in HBM)
   // Query units: without candidate lists a unit is `group` consecutive
   // queries that share every document tile read (query a of unit u is
   // u * group + a, its tokens in blocks a * bpq .. a * bpq + bpq - 1 of 16);
   // with candidate lists a unit is one query (group 1, bpq = query blocks).
   int32_t group;
   int32_t bpq;
-  int32_t pad;
+  // 64-byte column groups of a query row in LDS: nch * DCH * element size /
+  // 64 (the row zero-extended to whole chunks)
+  int32_t ncg;
   int64_t n_units;   // ceil(n_q / group)
   int64_t n_upairs;  // work pairs: n_units * n_docs, or the candidate count
 };
@@ -131,6 +133,9 @@ hipError_t launch_quantize(const float* src, int64_t n_tokens, int dim, int dt, 
 // ---- measured read ceiling ----
 hipError_t launch_stream_probe(const void* buf, size_t bytes, int variant, uint32_t* sink,
                                int grid, hipStream_t s);
+// ---- measured LDS gather ceiling (grid: one workgroup of 16 waves per CU) ----
+hipError_t launch_lds_probe(const void* buf, size_t bytes, int variant, int table_bytes,
+                            uint32_t* sink, int grid, hipStream_t s);
 
 // ---- device-side input checks (flags: caller's device int32) ----
 hipError_t launch_clear_flags(int32_t* flags, hipStream_t s);

@@ -15,6 +15,7 @@
 //   variant 5: variant 4 with the 4 KiB tiles dealt round-robin to the waves
 //              (all waves sweep the buffer together) instead of one
 //              contiguous share per wave
+// and the LDS gather ceiling (lds_gather_kernel below).
 #include "device_common.h"
 #include "kernels.h"
 
@@ -112,7 +113,100 @@ __global__ __launch_bounds__(256) void stream_read_lds_kernel(const u32x4* __res
   if (lane == 0) sink[w] = x;
 }
 
+// LDS gather ceiling: the rate at which the chip serves table lookups from
+// LDS, the bound of the PQ scorers (Sec. 4.3 Phase 2 gathers table entries;
+// the decode variant gathers codebook rows). Each workgroup (16 waves, one per
+// CU) fills a table of `slots` 16-byte entries in LDS, then every wave streams
+// its share of a byte buffer from HBM (non-temporal, 16 bytes per lane, four
+// steps in flight) and turns each 4-byte word into 8 table indices (its
+// rotations by 4-bit steps), each read with one LDS instruction, REPS times
+// per word with a different xor mask:
+//   variant 0: random 4-byte reads (ds_read_b32), REPS = 4
+//   variant 1: random 16-byte reads (ds_read_b128), REPS = 1
+//   variant 2: 16-byte reads whose 16 lanes per quarter-wave fall in 16
+//              distinct 16-byte bank groups (random row, slot low bits =
+//              lane % 16): conflict-free, the LDS read peak, REPS = 1
+// Every lane therefore performs 32 * REPS reads per 16 bytes streamed.
+template <int VARIANT>
+__global__ __launch_bounds__(1024) void lds_gather_kernel(const u32x4* __restrict__ buf, int64_t n16,
+                                                          int slots, uint32_t* __restrict__ sink) {
+  extern __shared__ u32x4 table[];
+  constexpr int REPS = VARIANT == 0 ? 4 : 1;
+  for (int i = threadIdx.x; i < slots; i += 1024)
+    table[i] = u32x4{(uint32_t)i * 2654435761u, (uint32_t)i ^ 0x9e3779b9u, (uint32_t)i + 7u,
+                     ~(uint32_t)i};
+  __syncthreads();
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  const int64_t nw = (int64_t)gridDim.x * 16;
+  const int64_t w = (int64_t)blockIdx.x * 16 + wv;
+  const int64_t units = n16 / 64;  // 1 KiB per wave step
+  const int64_t lo = units * w / nw, hi = units * (w + 1) / nw;
+  const uint32_t m16 = (uint32_t)slots - 1u, m4 = (uint32_t)slots * 4u - 1u;
+  const uint32_t* t4 = (const uint32_t*)table;
+  u32x4 acc = {0, 0, 0, 0};
+  for (int64_t u = lo; u < hi; u += 4) {
+    u32x4 c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t uu = u + j < hi ? u + j : hi - 1;
+      c[j] = __builtin_nontemporal_load(buf + uu * 64 + lane);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (u + j >= hi) break;  // wave-uniform
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int rep = 0; rep < REPS; ++rep) {
+          const uint32_t word = c[j][e] ^ (0x9e3779b9u * (uint32_t)rep);
+#pragma unroll
+          for (int sft = 0; sft < 8; ++sft) {
+            const uint32_t key = __builtin_amdgcn_alignbit(word, word, 4 * sft);
+            if constexpr (VARIANT == 0) {
+              acc.x ^= t4[key & m4];
+            } else if constexpr (VARIANT == 1) {
+              acc ^= table[key & m16];
+            } else {
+              acc ^= table[((key & m16) & ~15u) | (uint32_t)(lane & 15)];
+            }
+          }
+        }
+      }
+    }
+  }
+  uint32_t x = acc.x ^ acc.y ^ acc.z ^ acc.w;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x ^= __shfl_xor(x, m, 64);
+  if (lane == 0) sink[w] = x;
+}
+
+template <int VARIANT>
+hipError_t launch_lds_gather_t(const void* buf, int64_t n16, int slots, uint32_t* sink, int grid,
+                               hipStream_t s) {
+  auto k = lds_gather_kernel<VARIANT>;
+  const size_t lds = (size_t)slots * 16;
+  if (lds > 64 * 1024) {
+    hipError_t e =
+        hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k, dim3(grid), dim3(1024), lds, s, (const u32x4*)buf, n16, slots, sink);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_lds_probe(const void* buf, size_t bytes, int variant, int table_bytes,
+                            uint32_t* sink, int grid, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  const int slots = table_bytes / 16;
+  switch (variant) {
+    case 0: return launch_lds_gather_t<0>(buf, n16, slots, sink, grid, s);
+    case 1: return launch_lds_gather_t<1>(buf, n16, slots, sink, grid, s);
+    default: return launch_lds_gather_t<2>(buf, n16, slots, sink, grid, s);
+  }
+}
 
 hipError_t launch_stream_probe(const void* buf, size_t bytes, int variant, uint32_t* sink,
                                int grid, hipStream_t s) {

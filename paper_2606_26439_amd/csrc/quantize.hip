@@ -57,13 +57,13 @@ __device__ __forceinline__ int fp8_scale_exponent(float amax) {
   return e - 8 + (mant > 0x600000u ? 1 : 0) - bias;
 }
 
-// One wavefront per token; dim <= 1024 so each lane holds <= 16 values.
+// One wavefront per token; dim <= 1024 so each lane holds <= 16 values
+// (element j * 64 + lane, for those below dim).
 __global__ __launch_bounds__(256) void to_fp8_kernel(const float* __restrict__ src,
                                                      uint8_t* __restrict__ dst,
                                                      float* __restrict__ scales,
                                                      int64_t n_tokens, int dim) {
   const int lane = lane_id();
-  const int per = dim / 64;  // dim % 64 == 0
   for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < n_tokens;
        t += (int64_t)gridDim.x * 4) {
     const float* x = src + t * dim;
@@ -71,7 +71,8 @@ __global__ __launch_bounds__(256) void to_fp8_kernel(const float* __restrict__ s
     float amax = 0.f;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      if (j < per) {
+      v[j] = 0.f;
+      if (j * 64 + lane < dim) {
         v[j] = x[j * 64 + lane];
         amax = fmaxf(amax, fabsf(v[j]));
       }
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(256) void to_fp8_kernel(const float* __restrict__ s
     uint8_t* out = dst + t * dim;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      if (j < per) {
+      if (j * 64 + lane < dim) {
         unsigned int p = __builtin_amdgcn_cvt_pk_fp8_f32(v[j] * inv, 0.f, 0u, false);
         out[j * 64 + lane] = (uint8_t)(p & 0xFF);
       }

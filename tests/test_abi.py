@@ -33,7 +33,9 @@ def _csr(dtype=2, dim=128, n_sets=1, n_tokens=4, max_len=4, tokens=16, offsets=1
 
 
 @pytest.mark.parametrize("q,d,code", [
-    (dict(dim=96), dict(dim=96), 2),                  # dim not a multiple of 64
+    (dict(dim=100), dict(dim=100), 2),                # dim not a multiple of 16
+    (dict(dim=8), dict(dim=8), 2),                    # dim below 16
+    (dict(dim=1040), dict(dim=1040), 2),              # dim above 1024
     (dict(dtype=7), dict(), 1),                       # unknown dtype
     (dict(max_len=65), dict(), 2),                    # too many query tokens
     (dict(), dict(dim=256), 1),                       # dims differ
@@ -102,7 +104,7 @@ def test_validate_rejects_bad_host_arguments():
     cc = B.Cand(16, 16, 4)
     assert L.maxsim_validate(None, ctypes.byref(dc), ctypes.byref(cc), ctypes.c_void_p(16),
                              None) == 1
-    bad = _csr(dim=96)
+    bad = _csr(dim=100)
     assert L.maxsim_validate(None, ctypes.byref(bad), None, ctypes.c_void_p(16), None) == 2
     assert L.maxsim_validate_pq(None, None, None, ctypes.c_void_p(16), None) == 1
 
@@ -141,3 +143,22 @@ def test_residual_workspace_is_the_centroid_table():
                                    ctypes.c_void_p(256), need - 1, None) == 3
     assert L.maxsim_validate_residual(None, ctypes.byref(rc), None, None, None) == 1
     assert L.maxsim_validate_residual(None, None, None, ctypes.c_void_p(16), None) == 1
+
+
+@pytest.mark.parametrize("dim", [16, 32, 48, 96, 160, 400, 1024])
+def test_every_multiple_of_16_up_to_1024_is_accepted(dim):
+    # no queries: nothing to launch, so the call validates and returns OK on
+    # any machine; quantize with no tokens likewise
+    L = M.lib()
+    for dt in (0, 1, 2, 3):
+        qc = _csr(dtype=dt, dim=dim, n_sets=0, n_tokens=0, max_len=32, tokens=None,
+                  scales=16 if dt == 3 else None)
+        dc = _csr(dtype=dt, dim=dim, scales=16 if dt == 3 else None)
+        st = L.maxsim_score(ctypes.byref(qc), ctypes.byref(dc), None, ctypes.c_void_p(16), None,
+                            0, None)
+        assert st == 0, L.maxsim_last_error()
+        st = L.maxsim_score_unfused(ctypes.byref(qc), ctypes.byref(dc), ctypes.c_void_p(16),
+                                    None, 0, None)
+        assert st == 0, L.maxsim_last_error()
+        assert L.maxsim_quantize(ctypes.c_void_p(16), 0, dim, dt, ctypes.c_void_p(16),
+                                 ctypes.c_void_p(16) if dt == 3 else None, None) == 0

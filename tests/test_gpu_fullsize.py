@@ -98,6 +98,45 @@ def test_ragged_1m_docs_sampled_and_top100(ragged_1m, dtype):
     _release()
 
 
+def test_ragged_1m_f16_fused_and_unfused_top100_identical(ragged_1m):
+    # The headline comparison at its full size (1M ragged docs, one 32-token
+    # query, d = 128, FP16): the unfused comparator that materialises S and
+    # the fused scorer select the same top-100 ids, and both equal the exact
+    # top-100 of the oracle up to swaps between near-ties.
+    w = ragged_1m
+    qt, _ = M.quantize(torch.from_numpy(w["q"]).cuda(), "f16")
+    Q = M.Tokens(qt, torch.tensor([0, 32], device="cuda"), "f16", None, max_len=32)
+    dt, _ = M.quantize(w["d32"], "f16")
+    D = M.Tokens(dt, w["d_off_dev"], "f16", None, max_len=180)
+    seg = torch.tensor([0, N_DOCS], dtype=torch.int64, device="cuda")
+    fused = M.score(Q, D)
+    _, ids_f = M.topk(fused, seg, K)
+    ws = torch.empty(M.unfused_workspace_bytes(Q, D), dtype=torch.uint8, device="cuda")
+    unfused = M.score_unfused(Q, D, workspace=ws)
+    del ws
+    _, ids_u = M.topk(unfused, seg, K)
+    ids_f, ids_u = ids_f.cpu().numpy()[0], ids_u.cpu().numpy()[0]
+    assert set(ids_f.tolist()) == set(ids_u.tolist())
+    qv, _ = oracle.exact_values(w["q"], "f16")
+
+    def o1(docs):
+        rows, off = doc_rows(w["d_off"], docs)
+        x = w["d32"][torch.from_numpy(rows).cuda()].cpu().numpy()
+        dv, _ = oracle.exact_values(x, "f16")
+        return oracle.maxsim(qv, [0, 32], dv, off)
+
+    tol = REL_TOL_DT["f16"] * 32
+    exact = _exact_topk_by_id(fused, 4 * tol, o1)
+    assert_topk_matches_exact(ids_f, None, exact, K, 2 * tol, "1M f16 fused")
+    assert_topk_matches_exact(ids_u, None, exact, K, 2 * tol, "1M f16 unfused")
+    # and the scores themselves agree within the gate on a sample
+    samp = torch.from_numpy(np.sort(W.rng(23).choice(N_DOCS, 2000, replace=False))).cuda()
+    assert_close_o1(unfused[samp].cpu().numpy(), fused[samp].cpu().numpy().astype(np.float64),
+                    "unfused vs fused", "f16")
+    del dt, D, fused, unfused
+    _release()
+
+
 @pytest.mark.parametrize("dim", [64, 256, 512, 768])
 def test_dimension_tiling_500k_docs_sampled(dim):
     B, nd = 500_000, 128
