@@ -259,6 +259,38 @@ maxsim_status maxsim_topk(const float* scores, const int64_t* seg_offsets, int64
                           maxsim_stream_t stream);
 
 /*
+ * Fused scoring with the top-k in the scorer's epilogue (the retrieval step
+ * of the paper's end-to-end pipeline, Evaluation "End-to-End Retrieval
+ * Latency", for the whole collection as in the large-scale extrapolation):
+ * the same scores as maxsim_score, but none is stored. Each workgroup of the
+ * scoring launch keeps its scores' ranking keys on chip and selects the k best
+ * of each query's share of its range (exact radix select); a second, small
+ * launch merges the per-workgroup parts of every query.
+ *   queries, docs, cand  as for maxsim_score.
+ *   k                    1 <= k <= 1024.
+ *   out_scores, out_ids  [n_queries * k] device arrays: row a holds query a's
+ *                        k best documents by score descending, then id
+ *                        ascending, padded with (-inf, -1); ids are document
+ *                        indices, or the candidate ids with candidate lists.
+ *                        Bit-identical to maxsim_score followed by
+ *                        maxsim_topk over per-query segments (ids NULL, or the
+ *                        candidate doc_ids).
+ *   workspace            maxsim_score_topk_workspace_size() bytes, 16-byte
+ *                        aligned, contents ignored: per-workgroup parts and a
+ *                        4-byte key per (query, document) pair for workgroups
+ *                        whose range does not fit their LDS (SIZE_MAX: too
+ *                        large for the address space).
+ * Errors: as maxsim_score; k out of range -> MAXSIM_EINVAL; workspace short
+ * -> MAXSIM_EWORKSPACE. Asynchronous on `stream` (two launches).
+ */
+size_t maxsim_score_topk_workspace_size(const maxsim_csr* queries, const maxsim_csr* docs,
+                                        const maxsim_candidates* cand, int32_t k);
+maxsim_status maxsim_score_topk(const maxsim_csr* queries, const maxsim_csr* docs,
+                                const maxsim_candidates* cand, int32_t k, float* out_scores,
+                                int32_t* out_ids, void* workspace, size_t ws_bytes,
+                                maxsim_stream_t stream);
+
+/*
  * Tile/launch-shape autotuner (Evaluation, "Tile Size Sensitivity"): times
  * every candidate launch configuration of the fused kernel on the given
  * problem with HIP events (synchronises `stream`), keeps the fastest for the

@@ -10,5 +10,6 @@ from ._binding import (DTYPES, ELEM_BYTES, Candidates, MaxSimError, PQDocs,  # n
                        ResidualDocs, Tokens, autotune, default_tune_cache, lib,
                        load_tune_cache, pq_autotune, pq_score, quantize, residual_autotune,
                        residual_score,
-                       residual_workspace_bytes, score, score_unfused, stream_probe, lds_probe, topk,
+                       residual_workspace_bytes, score, score_topk, score_topk_workspace_bytes,
+                       score_unfused, stream_probe, lds_probe, topk,
                        topk_workspace_bytes, unfused_workspace_bytes, validate)

@@ -77,6 +77,10 @@ def lib():
     L.maxsim_score_workspace_size.argtypes = [_P(CSR), _P(CSR), _P(Cand)]
     L.maxsim_score_workspace_size.restype = ctypes.c_size_t
     L.maxsim_score.argtypes = [_P(CSR), _P(CSR), _P(Cand), _vp, _vp, ctypes.c_size_t, _vp]
+    L.maxsim_score_topk_workspace_size.argtypes = [_P(CSR), _P(CSR), _P(Cand), ctypes.c_int32]
+    L.maxsim_score_topk_workspace_size.restype = ctypes.c_size_t
+    L.maxsim_score_topk.argtypes = [_P(CSR), _P(CSR), _P(Cand), ctypes.c_int32, _vp, _vp, _vp,
+                                    ctypes.c_size_t, _vp]
     L.maxsim_score_unfused_workspace_size.argtypes = [_P(CSR), _P(CSR)]
     L.maxsim_score_unfused_workspace_size.restype = ctypes.c_size_t
     L.maxsim_score_unfused.argtypes = [_P(CSR), _P(CSR), _vp, _vp, ctypes.c_size_t, _vp]
@@ -109,7 +113,8 @@ def lib():
                                       _vp]
     L.maxsim_lds_probe.argtypes = [_vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _vp,
                                    ctypes.c_int64, _vp]
-    for name in ("maxsim_quantize", "maxsim_score", "maxsim_score_unfused", "maxsim_pq_score",
+    for name in ("maxsim_quantize", "maxsim_score", "maxsim_score_topk", "maxsim_score_unfused",
+                 "maxsim_pq_score",
                  "maxsim_topk", "maxsim_autotune", "maxsim_pq_autotune",
                  "maxsim_load_tune_cache", "maxsim_stream_probe", "maxsim_lds_probe",
                  "maxsim_validate",
@@ -243,6 +248,34 @@ def score(q: Tokens, d: Tokens, cand: Candidates = None, out=None, stream=None):
     _check(lib().maxsim_score(ctypes.byref(qc), ctypes.byref(dc),
                               ctypes.byref(cc) if cc is not None else None, _ptr(out), None, 0,
                               _stream(stream)))
+    return out
+
+
+def score_topk_workspace_bytes(q: Tokens, d: Tokens, k: int, cand: Candidates = None) -> int:
+    qc, dc = q.csr(), d.csr()
+    cc = cand.c() if cand is not None else None
+    return int(lib().maxsim_score_topk_workspace_size(
+        ctypes.byref(qc), ctypes.byref(dc), ctypes.byref(cc) if cc is not None else None, k))
+
+
+def score_topk(q: Tokens, d: Tokens, k: int, cand: Candidates = None, workspace=None,
+               out=None, stream=None):
+    """Fused scoring with the top-k in the scorer's epilogue (no score array):
+    (scores [n_q, k], ids [n_q, k]) by score descending, then id ascending;
+    ids are document indices, or candidate ids with candidate lists."""
+    dev = d.offsets.device
+    if out is None:
+        out = (torch.empty((q.n_sets, k), dtype=torch.float32, device=dev),
+               torch.empty((q.n_sets, k), dtype=torch.int32, device=dev))
+    if workspace is None:
+        workspace = torch.empty(max(score_topk_workspace_bytes(q, d, k, cand), 1),
+                                dtype=torch.uint8, device=dev)
+    qc, dc = q.csr(), d.csr()
+    cc = cand.c() if cand is not None else None
+    _check(lib().maxsim_score_topk(ctypes.byref(qc), ctypes.byref(dc),
+                                   ctypes.byref(cc) if cc is not None else None, k,
+                                   _ptr(out[0]), _ptr(out[1]), _ptr(workspace),
+                                   workspace.numel(), _stream(stream)))
     return out
 
 

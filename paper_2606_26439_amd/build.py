@@ -54,6 +54,8 @@ def _deps(src):
     hdrs.append(os.path.join(HERE, "..", "include", "maxsim.h"))
     if src == "fused_inst.hip":
         hdrs.append(os.path.join(CSRC, "fused_impl.h"))
+    if src in ("fused_inst.hip", "topk.hip"):
+        hdrs.append(os.path.join(CSRC, "select_impl.h"))
     return [os.path.join(CSRC, src)] + hdrs + [os.path.abspath(__file__)]
 
 

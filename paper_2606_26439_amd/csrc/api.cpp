@@ -176,7 +176,8 @@ struct FusedPlan {
 };
 
 maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_candidates* cand,
-                         float* scores, FusedPlan& pl, bool group_queries = true) {
+                         float* scores, FusedPlan& pl, bool group_queries = true,
+                         bool need_scores = true) {
   maxsim_status st = check_csr(q, "queries", true);
   if (st) return st;
   if ((st = check_csr(d, "docs", false))) return st;
@@ -192,7 +193,7 @@ maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_
   } else {
     n_pairs = q->n_sets * d->n_sets;
   }
-  if (n_pairs > 0 && !scores) return fail(MAXSIM_EINVAL, "scores is NULL");
+  if (n_pairs > 0 && !scores && need_scores) return fail(MAXSIM_EINVAL, "scores is NULL");
   pl.dt = q->dtype;
   // d-chunk width: 128 (the paper's dimension tiling), 64 when d > 128 is not
   // a multiple of 128, and 256 for 1- and 2-byte rows of d >= 512 (same k
@@ -255,8 +256,23 @@ maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_
   return MAXSIM_OK;
 }
 
-maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s) {
-  if (pl.n_pairs == 0) return MAXSIM_OK;
+// A fused launch ready to go: kernel, parameters, dynamic LDS and grid.
+struct FusedLaunch {
+  FusedFns fns{};
+  FusedParams P{};
+  size_t lds = 0;
+  int64_t grid = 0;
+};
+
+int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Kernel choice, LDS layout and grid of a fused launch (topk_k > 0: with the
+// top-k epilogue, whose key slots take the LDS the tuned occupancy leaves).
+maxsim_status prepare_fused(const FusedPlan& pl, const FusedCfg& cfg, int topk_k, FusedLaunch& L) {
   DevInfo di = device_info();
   // 256-wide chunks exist only with LDS-staged tiles, and only where their
   // ring fits beside one copy of the query blocks; else 128-wide
@@ -290,13 +306,70 @@ maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s)
   int occ = fns.occupancy(lds);
   if (occ <= 0) return fail(MAXSIM_EHIP, "fused kernel does not fit on a compute unit");
   int per_cu = cfg.wg_per_cu > 0 ? std::min(cfg.wg_per_cu, occ) : occ;
+  P.topk_k = 0;
+  P.key_cap = 0;
+  P.lds_keys_off = 0;
+  P.sel_cap = 0;
+  if (topk_k > 0) {
+    // selection scratch (reusing the query/ring area), then the key slots and
+    // the wave ranges; the slots get what the tuned occupancy leaves of LDS
+    P.topk_k = topk_k;
+    P.sel_cap = std::min(2048, std::max(256, pow2_at_least(2 * topk_k)));
+    const size_t head = (std::max(lds, fused_topk_scratch_bytes(P.sel_cap)) + 15) & ~(size_t)15;
+    const size_t ranges = (size_t)cfg.nw * 16;
+    const size_t share = di.max_lds / (size_t)per_cu;
+    int64_t slots = share > head + ranges ? (int64_t)((share - head - ranges) / 4) : 0;
+    slots = std::min<int64_t>(slots, 65536);
+    slots -= slots % cfg.nw;
+    P.key_cap = (int32_t)slots;
+    P.lds_keys_off = (int32_t)head;
+    lds = head + (size_t)slots * 4 + ranges;
+    if (lds > di.max_lds) return fail(MAXSIM_EUNSUPPORTED, "top-k epilogue needs %zu bytes of LDS", lds);
+    occ = fns.occupancy(lds);
+    if (occ <= 0) return fail(MAXSIM_EHIP, "fused top-k kernel does not fit on a compute unit");
+    per_cu = std::min(per_cu, occ);
+  }
   int64_t grid = (int64_t)per_cu * di.cus;
   int64_t need = (pl.P.n_upairs + cfg.nw - 1) / cfg.nw;  // at least one work pair per wave
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
-  hipError_t e = fns.launch(P, (int)grid, lds, s);
+  if (topk_k > 0 && grid > MERGE_MAX_GRID) grid = MERGE_MAX_GRID;
+  L.fns = fns;
+  L.P = P;
+  L.lds = lds;
+  L.grid = grid;
+  return MAXSIM_OK;
+}
+
+maxsim_status run_fused(const FusedPlan& pl, const FusedCfg& cfg, hipStream_t s) {
+  if (pl.n_pairs == 0) return MAXSIM_OK;
+  FusedLaunch L;
+  maxsim_status st = prepare_fused(pl, cfg, 0, L);
+  if (st) return st;
+  hipError_t e = L.fns.launch(L.P, (int)L.grid, L.lds, s);
   if (e != hipSuccess) return hip_fail(e, "fused MaxSim launch");
   return MAXSIM_OK;
+}
+
+// Workspace of the fused top-k: workgroup starts, part counts, part keys and
+// the key spill array, each 256-byte aligned.
+struct TopkLayout {
+  size_t wg_lo = 0, cnt = 0, keys = 0, spill = 0, total = 0;
+};
+
+bool topk_layout(const FusedLaunch& L, int k, TopkLayout& T) {
+  const FusedParams& P = L.P;
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t n_slots = (size_t)(L.grid + P.n_units) * (size_t)P.group;
+  size_t keys_b = 0, spill_b = 0;
+  if (__builtin_mul_overflow(n_slots, (size_t)k * 8, &keys_b)) return false;
+  if (__builtin_mul_overflow((size_t)P.n_upairs, (size_t)P.group * 4, &spill_b)) return false;
+  T.wg_lo = 0;
+  T.cnt = up((size_t)L.grid * 8);
+  T.keys = T.cnt + up(n_slots * 4);
+  T.spill = T.keys + up(keys_b);
+  if (__builtin_add_overflow(T.spill, up(spill_b), &T.total)) return false;
+  return true;
 }
 
 // ------------------------------------------------------------- JSON cache --
@@ -392,6 +465,90 @@ maxsim_status maxsim_score(const maxsim_csr* queries, const maxsim_csr* docs,
   return run_fused(pl, cfg, (hipStream_t)stream);
 }
 
+namespace {
+
+// Plan of a fused score + top-k call: the scoring launch (when there are work
+// pairs) and its workspace layout.
+maxsim_status plan_score_topk(const maxsim_csr* q, const maxsim_csr* d,
+                              const maxsim_candidates* cand, int32_t k, FusedPlan& pl,
+                              FusedLaunch& L, TopkLayout& T, bool* overflow = nullptr) {
+  if (k < 1 || k > 1024) return fail(MAXSIM_EINVAL, "score_topk: k=%d must be in [1, 1024]", k);
+  maxsim_status st = plan_fused(q, d, cand, nullptr, pl, true, /*need_scores=*/false);
+  if (st) return st;
+  if (pl.n_pairs > 0) {
+    FusedCfg cfg = lookup_cfg({pl.dt, q->dim, pl.nqb}, pl.qreg ? 0 : pl.lds, pl.dch);
+    if ((st = prepare_fused(pl, cfg, k, L))) return st;
+  } else {
+    L.P = pl.P;
+    L.grid = 0;
+  }
+  if (!topk_layout(L, k, T)) {
+    if (overflow) *overflow = true;
+    return fail(MAXSIM_EUNSUPPORTED, "score_topk: workspace exceeds the address space");
+  }
+  return MAXSIM_OK;
+}
+
+}  // namespace
+
+size_t maxsim_score_topk_workspace_size(const maxsim_csr* q, const maxsim_csr* d,
+                                        const maxsim_candidates* cand, int32_t k) {
+  FusedPlan pl;
+  FusedLaunch L;
+  TopkLayout T;
+  bool overflow = false;
+  const std::string saved = g_err;
+  maxsim_status st = plan_score_topk(q, d, cand, k, pl, L, T, &overflow);
+  g_err = saved;
+  if (overflow) return SIZE_MAX;
+  return st ? 0 : T.total;
+}
+
+maxsim_status maxsim_score_topk(const maxsim_csr* queries, const maxsim_csr* docs,
+                                const maxsim_candidates* cand, int32_t k, float* out_scores,
+                                int32_t* out_ids, void* workspace, size_t ws_bytes,
+                                maxsim_stream_t stream) {
+  FusedPlan pl;
+  FusedLaunch L;
+  TopkLayout T;
+  maxsim_status st = plan_score_topk(queries, docs, cand, k, pl, L, T);
+  if (st) return st;
+  if (queries->n_sets == 0) return MAXSIM_OK;
+  if (!out_scores || !out_ids) return fail(MAXSIM_EINVAL, "score_topk: NULL output");
+  if (!workspace || ws_bytes < T.total)
+    return fail(MAXSIM_EWORKSPACE, "score_topk: workspace needs %zu bytes", T.total);
+  if (!aligned(workspace, 16))
+    return fail(MAXSIM_EINVAL, "score_topk: workspace must be 16-byte aligned");
+  char* ws = (char*)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  if (L.grid > 0) {
+    FusedParams& P = L.P;
+    P.scores = nullptr;
+    P.wg_lo = (int64_t*)(ws + T.wg_lo);
+    P.part_cnt = (uint32_t*)(ws + T.cnt);
+    P.part_keys = (uint64_t*)(ws + T.keys);
+    P.key_spill = (uint32_t*)(ws + T.spill);
+    hipError_t e = L.fns.launch(P, (int)L.grid, L.lds, s);
+    if (e != hipSuccess) return hip_fail(e, "fused score_topk launch");
+  }
+  MergeParams M{};
+  M.cand_off = pl.P.cand_off;
+  M.n_q = queries->n_sets;
+  M.n_docs = pl.P.n_docs;
+  M.n_upairs = pl.P.n_upairs;
+  M.group = pl.P.group;
+  M.grid = (int32_t)L.grid;
+  M.k = k;
+  M.wg_lo = (const int64_t*)(ws + T.wg_lo);
+  M.part_keys = (const uint64_t*)(ws + T.keys);
+  M.part_cnt = (const uint32_t*)(ws + T.cnt);
+  M.out_scores = out_scores;
+  M.out_ids = out_ids;
+  hipError_t e = launch_topk_merge(M, s);
+  if (e != hipSuccess) return hip_fail(e, "top-k merge launch");
+  return MAXSIM_OK;
+}
+
 size_t maxsim_score_unfused_workspace_size(const maxsim_csr* q, const maxsim_csr* d) {
   if (!q || !d || q->n_sets < 0 || d->n_tokens < 0) return 0;
   // S holds n_q x n_tokens rows of the query-capacity columns, FP32
@@ -438,11 +595,6 @@ struct PqPlan {
   int variant = 0;
 };
 
-int pow2_at_least(int x) {
-  int p = 1;
-  while (p < x) p <<= 1;
-  return p;
-}
 
 PqKey pq_key(const maxsim_csr* q, const maxsim_pq_docs* d, const maxsim_candidates* cand) {
   return {d->M, d->dsub, pow2_at_least(std::max(1, (q->max_len + 15) / 16)), cand ? 1 : 0};

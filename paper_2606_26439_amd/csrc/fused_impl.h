@@ -32,6 +32,7 @@
 #pragma once
 #include "device_common.h"
 #include "kernels.h"
+#include "select_impl.h"
 
 namespace fused_detail {
 
@@ -161,6 +162,57 @@ constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (0x7 << 4
 // expcnt at their maxima
 constexpr int lgkmcnt0_imm() { return 0xF | (0x3 << 14) | (0x7 << 4); }
 
+// Fused top-k, after every wave of the workgroup has stored its keys: for
+// each query with work pairs in the workgroup's range, the k best ranking keys
+// of those pairs (exact radix select over the wave key slots, or the spill
+// array for a wave whose range did not fit them) go to the query's part slot.
+// ranges[w], ranges[NW + w]: first and end work pair of wave w (contiguous).
+template <int NW>
+__device__ void topk_epilogue(const FusedParams& P, u32x4* lds, const int64_t* ranges) {
+  using namespace topk_detail;
+  const int k = P.topk_k, cap = P.sel_cap, G = P.group;
+  uint64_t* buf = (uint64_t*)lds;
+  uint32_t* hist = (uint32_t*)((char*)lds + (size_t)cap * 8);
+  const uint32_t* lkeys = (const uint32_t*)((const char*)lds + P.lds_keys_off);
+  const int key_slots = P.key_cap / NW;
+  const int64_t lo = ranges[0], hi = ranges[2 * NW - 1];
+  if (threadIdx.x == 0) P.wg_lo[blockIdx.x] = lo;
+  if (lo >= hi) return;
+  const bool dense = P.cand_off == nullptr;
+  int64_t a0, a1;  // units with pairs in [lo, hi)
+  if (dense) {
+    a0 = lo / P.n_docs;
+    a1 = (hi - 1) / P.n_docs;
+  } else {
+    a0 = wave_owner(P.cand_off, P.n_q, lo);
+    a1 = wave_owner(P.cand_off, P.n_q, hi - 1);
+  }
+  for (int64_t a = a0; a <= a1; ++a) {
+    const int64_t s0 = dense ? a * P.n_docs : P.cand_off[a];
+    const int64_t s1 = dense ? s0 + P.n_docs : P.cand_off[a + 1];
+    const int64_t p0 = lo > s0 ? lo : s0, p1 = hi < s1 ? hi : s1;
+    if (p0 >= p1) continue;
+    for (int gq = 0; gq < G; ++gq) {
+      if (a * G + gq >= P.n_q) break;
+      auto get = [&](int64_t i) -> uint64_t {
+        const int64_t p = p0 + i;
+        int w = 0;  // the wave whose range holds p: the last one starting at or before it
+#pragma unroll
+        for (int v = 1; v < NW; ++v)
+          if (ranges[v] <= p) w = v;
+        const int64_t wl = ranges[w], wh = ranges[NW + w];
+        const uint32_t key = (wh - wl) * G <= key_slots ? lkeys[w * key_slots + (p - wl) * G + gq]
+                                                        : P.key_spill[p * G + gq];
+        const uint32_t id = dense ? (uint32_t)(p - s0) : (uint32_t)P.cand_ids[p];
+        return rank_key(key, id);
+      };
+      const int64_t slot = ((int64_t)blockIdx.x + a) * G + gq;
+      const int cnt = block_topk(p1 - p0, k, get, hist, buf, cap, P.part_keys + slot * k);
+      if (threadIdx.x == 0) P.part_cnt[slot] = (uint32_t)cnt;
+    }
+  }
+}
+
 // Where a wave's query operand lives (QM):
 //   Q_SHARED  one LDS copy per workgroup (large d); the workgroup's waves
 //             stage each query they cross together, with barriers;
@@ -213,6 +265,10 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
   const int64_t pe = PERWAVE ? my_hi : uniform64(wave_range_begin(P, wg0 + NW, W));
   // this wave's query operand in LDS (shared: the workgroup's copy)
   u32x4* qw = q_lds + (QM == Q_WAVE ? (size_t)wave * NQB * ncg * 64 : 0);
+  // fused top-k: this wave's key slots, used when its whole range fits them
+  const int key_slots = P.key_cap / NW;
+  const bool keys_in_lds = (my_hi - my_lo) * P.group <= key_slots;
+  uint32_t* const wave_keys = (uint32_t*)((char*)q_lds + P.lds_keys_off) + wave * key_slots;
 
   while (pb < pe) {
     int64_t a, qend;  // a: the unit (with candidate lists: the query)
@@ -294,7 +350,15 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     auto store = [&](int64_t pp, int gq, float v) {
       // (NaN as a bit pattern: this file is compiled assuming no NaN arithmetic)
       if ((qmask >> (16 + gq)) & 1u) v = __builtin_bit_cast(float, 0x7fc00000u);
-      P.scores[pp + sbase + (int64_t)gq * P.n_docs] = v;
+      if (P.topk_k > 0) {
+        const uint32_t key = topk_detail::score_key(v);
+        if (keys_in_lds)
+          wave_keys[(pp - my_lo) * P.group + gq] = key;
+        else
+          P.key_spill[pp * P.group + gq] = key;
+      } else {
+        P.scores[pp + sbase + (int64_t)gq * P.n_docs] = v;
+      }
     };
 
     // ---- prefetch cursor over the (pair, tile, chunk) steps of [lo, hi) ----
@@ -605,6 +669,18 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     // the next segment's fills reuse the slots
     if constexpr (STAGE) __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
     pb = se;
+  }
+
+  if (P.topk_k > 0) {
+    // publish the wave ranges next to the key slots; once every wave is done
+    // the query operand and ring area is free for the selection
+    int64_t* ranges = (int64_t*)((char*)q_lds + P.lds_keys_off + (size_t)P.key_cap * 4);
+    if (lane == 0) {
+      ranges[wave] = my_lo;
+      ranges[NW + wave] = my_hi;
+    }
+    __syncthreads();
+    topk_epilogue<NW>(P, q_lds, ranges);
   }
 }
 

@@ -35,7 +35,46 @@ struct FusedParams {
   int32_t ncg;
   int64_t n_units;   // ceil(n_q / group)
   int64_t n_upairs;  // work pairs: n_units * n_docs, or the candidate count
+  // Fused top-k (topk_k > 0): a score is not stored; its ranking key goes to
+  // the key array of the wave that computed it (LDS, key_cap / NW slots per
+  // wave, at byte lds_keys_off of the dynamic LDS), or to key_spill[pair *
+  // group + query of the unit] when the wave's range does not fit; after its
+  // waves finish, the workgroup writes the top-k keys of each query's part of
+  // its range to slot (workgroup + unit) * group + query of part_keys (k keys)
+  // and part_cnt, and its first work pair to wg_lo[workgroup].
+  int32_t topk_k;
+  int32_t sel_cap;       // sort-buffer keys of the selection (power of two >= max(k, 64))
+  int32_t key_cap;       // LDS key slots of the workgroup (a multiple of its wave count)
+  int32_t lds_keys_off;  // bytes; the wave ranges follow the key slots
+  uint32_t* key_spill;   // [n_upairs * group]
+  int64_t* wg_lo;        // [grid]
+  uint64_t* part_keys;   // [(grid + n_units) * group * topk_k]
+  uint32_t* part_cnt;    // [(grid + n_units) * group]
 };
+
+// Merge of the fused scorer's per-workgroup top-k parts (one workgroup per
+// query): the k best keys of every part that covers the query.
+struct MergeParams {
+  const int64_t* cand_off;  // nullptr: every query against every doc
+  int64_t n_q;
+  int64_t n_docs;
+  int64_t n_upairs;
+  int32_t group;
+  int32_t grid;  // workgroups of the scoring launch
+  int32_t k;
+  int32_t pad;
+  const int64_t* wg_lo;
+  const uint64_t* part_keys;
+  const uint32_t* part_cnt;
+  float* out_scores;  // [n_q * k]
+  int32_t* out_ids;   // [n_q * k]
+};
+// LDS bytes the fused scorer's top-k epilogue needs at offset 0 (it reuses
+// the query and ring area once every wave has finished), for a sort buffer
+// of sel_cap keys.
+size_t fused_topk_scratch_bytes(int sel_cap);
+constexpr int MERGE_MAX_GRID = 4096;
+hipError_t launch_topk_merge(const MergeParams& M, hipStream_t s);
 
 typedef hipError_t (*fused_launch_fn)(const FusedParams&, int grid, size_t lds, hipStream_t);
 typedef int (*fused_occ_fn)(size_t lds);

@@ -20,8 +20,13 @@
 // Integer keys only: the result is exact and independent of launch shape.
 #include "device_common.h"
 #include "kernels.h"
+#include "select_impl.h"
 
 namespace {
+
+using topk_detail::bitonic_desc;
+using topk_detail::key_score;
+using topk_detail::score_key;
 
 constexpr int TK_THREADS = 256;
 constexpr int TK_SORT_THREADS = 1024;
@@ -43,16 +48,6 @@ struct SegWs {
 __host__ __device__ inline size_t seg_ws_bytes() {
   size_t b = sizeof(SegWs) + (size_t)(TK_MAXK + BOUND_CAP) * 8;
   return (b + 255) & ~(size_t)255;
-}
-
-__device__ __forceinline__ uint32_t score_key(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return 0u;  // NaN ranks last
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-__device__ __forceinline__ float key_score(uint32_t k) {
-  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
 }
 
 __device__ __forceinline__ uint64_t full_key(uint32_t sk, const int32_t* ids, int64_t i,
@@ -194,25 +189,6 @@ __global__ __launch_bounds__(TK_THREADS) void topk_compact_kernel(
   }
 }
 
-__device__ void bitonic_desc(uint64_t* keys, int n) {
-  for (int size = 2; size <= n; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        int j = i ^ stride;
-        if (j > i) {
-          bool desc = (i & size) == 0;
-          uint64_t a = keys[i], b = keys[j];
-          if (desc ? (a < b) : (a > b)) {
-            keys[i] = b;
-            keys[j] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
 __global__ __launch_bounds__(TK_SORT_THREADS) void topk_sort_kernel(
     const float* __restrict__ scores, const int64_t* __restrict__ seg_off,
     const int32_t* __restrict__ ids, void* ws, int k, float* __restrict__ out_scores,
@@ -330,5 +306,82 @@ hipError_t launch_topk(const float* scores, const int64_t* seg_off, int64_t n_se
                      k);
   hipLaunchKernelGGL(topk_sort_kernel, dim3((unsigned)n_seg), dim3(TK_SORT_THREADS), 0, st, scores,
                      seg_off, ids, ws, k, out_scores, out_ids);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Merge of the fused scorer's top-k parts: one workgroup per query. The
+// workgroups of the scoring launch whose ranges cover the query's work pairs
+// [ps, pe) are b0 .. b1 (wg_lo is non-decreasing); each non-empty one left
+// the k best keys of its share in part slot (b + unit) * group + query of the
+// unit. Missing part entries read as key 0, below every real key, so the
+// query's top-k is the top-k of the concatenated parts; key 0 in the result
+// means fewer than k candidates and becomes (-inf, -1).
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int MERGE_THREADS = 1024;
+constexpr int MERGE_CAP = 2048;  // sort buffer: >= 2 * max k
+
+__global__ __launch_bounds__(MERGE_THREADS) void topk_merge_kernel(MergeParams M) {
+  using namespace topk_detail;
+  __shared__ uint64_t buf[MERGE_CAP];
+  __shared__ uint32_t hist[SEL_HIST_WORDS];
+  __shared__ uint32_t cnts[MERGE_MAX_GRID];
+  const int64_t qa = blockIdx.x;
+  const int G = M.group, k = M.k;
+  const bool dense = M.cand_off == nullptr;
+  const int64_t a = dense ? qa / G : qa;
+  const int gq = dense ? (int)(qa % G) : 0;
+  const int64_t ps = dense ? a * M.n_docs : M.cand_off[qa];
+  const int64_t pe = dense ? ps + M.n_docs : M.cand_off[qa + 1];
+  float* os = M.out_scores + qa * k;
+  int32_t* oi = M.out_ids + qa * k;
+  if (ps >= pe) {
+    for (int i = threadIdx.x; i < k; i += MERGE_THREADS) {
+      os[i] = -__builtin_inff();
+      oi[i] = -1;
+    }
+    return;
+  }
+  auto R = [&](int64_t b) -> int64_t { return b >= M.grid ? M.n_upairs : M.wg_lo[b]; };
+  // the last workgroup b < grid with R(b) <= x
+  auto last_at_or_before = [&](int64_t x) -> int64_t {
+    int64_t lo = 0, hi = M.grid - 1;  // R(0) = 0 <= x
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (R(mid) <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
+  const int64_t b0 = last_at_or_before(ps), b1 = last_at_or_before(pe - 1);
+  const int nb = (int)(b1 - b0 + 1);
+  for (int i = threadIdx.x; i < nb; i += MERGE_THREADS) {
+    const int64_t b = b0 + i;
+    cnts[i] = R(b) < R(b + 1) ? M.part_cnt[(b + a) * G + gq] : 0u;
+  }
+  __syncthreads();
+  auto get = [&](int64_t i) -> uint64_t {
+    const int bi = (int)(i / k);
+    const int j = (int)(i - (int64_t)bi * k);
+    return (uint32_t)j < cnts[bi] ? M.part_keys[((b0 + bi + a) * G + gq) * k + j] : 0ull;
+  };
+  block_topk((int64_t)nb * k, k, get, hist, buf, MERGE_CAP, buf);
+  for (int i = threadIdx.x; i < k; i += MERGE_THREADS) {
+    const uint64_t key = buf[i];
+    os[i] = key == 0ull ? -__builtin_inff() : key_score((uint32_t)(key >> 32));
+    oi[i] = key == 0ull ? -1 : key_id(key);
+  }
+}
+
+}  // namespace
+
+size_t fused_topk_scratch_bytes(int sel_cap) {
+  return (size_t)sel_cap * 8 + (size_t)topk_detail::SEL_HIST_WORDS * 4;
+}
+
+hipError_t launch_topk_merge(const MergeParams& M, hipStream_t st) {
+  if (M.n_q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)M.n_q), dim3(MERGE_THREADS), 0, st, M);
   return hipGetLastError();
 }

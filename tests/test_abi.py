@@ -162,3 +162,18 @@ def test_every_multiple_of_16_up_to_1024_is_accepted(dim):
         assert st == 0, L.maxsim_last_error()
         assert L.maxsim_quantize(ctypes.c_void_p(16), 0, dim, dt, ctypes.c_void_p(16),
                                  ctypes.c_void_p(16) if dt == 3 else None, None) == 0
+
+
+def test_score_topk_validation():
+    L = M.lib()
+    qc, dc = _csr(), _csr()
+    for k in (0, -3, 1025):
+        st = L.maxsim_score_topk(ctypes.byref(qc), ctypes.byref(dc), None, k, ctypes.c_void_p(16),
+                                 ctypes.c_void_p(16), None, 0, None)
+        assert st == 1, L.maxsim_last_error()
+        assert L.maxsim_score_topk_workspace_size(ctypes.byref(qc), ctypes.byref(dc), None, k) == 0
+    bad = _csr(dim=100)
+    st = L.maxsim_score_topk(ctypes.byref(bad), ctypes.byref(bad), None, 10, ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), None, 0, None)
+    assert st == 2, L.maxsim_last_error()
+    assert L.maxsim_score_topk(None, ctypes.byref(dc), None, 10, None, None, None, 0, None) == 1
