@@ -291,6 +291,30 @@ maxsim_status maxsim_score_topk(const maxsim_csr* queries, const maxsim_csr* doc
                                 maxsim_stream_t stream);
 
 /*
+ * maxsim_score_topk for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same two launches and the same results, bit for bit, with
+ * the workspace taken from a fixed scratch array of
+ * MAXSIM_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends. The call allocates nothing; the caller still owns
+ * the queries, documents, candidates and outputs (as for maxsim_score_topk).
+ *   queries, docs, cand, k, out_scores, out_ids, stream
+ *                        as for maxsim_score_topk.
+ * Errors: as maxsim_score_topk; a problem whose
+ * maxsim_score_topk_workspace_size() exceeds MAXSIM_NOALLOC_SCRATCH_BYTES ->
+ * MAXSIM_EWORKSPACE (nothing enqueued). The scratch needs no clearing
+ * between calls (every word a launch reads was written earlier in the same
+ * call) and keeps the last call's contents. All calls on one GPU share its
+ * scratch: calls that overlap on one GPU (on different streams, or from
+ * different host threads without ordering) race and give undefined results.
+ */
+#define MAXSIM_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+maxsim_status maxsim_score_topk_noalloc(const maxsim_csr* queries, const maxsim_csr* docs,
+                                        const maxsim_candidates* cand, int32_t k,
+                                        float* out_scores, int32_t* out_ids,
+                                        maxsim_stream_t stream);
+
+/*
  * Tile/launch-shape autotuner (Evaluation, "Tile Size Sensitivity"): times
  * every candidate launch configuration of the fused kernel on the given
  * problem with HIP events (synchronises `stream`), keeps the fastest for the

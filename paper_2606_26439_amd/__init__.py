@@ -10,6 +10,7 @@ from ._binding import (DTYPES, ELEM_BYTES, Candidates, MaxSimError, PQDocs,  # n
                        ResidualDocs, Tokens, autotune, default_tune_cache, lib,
                        load_tune_cache, pq_autotune, pq_score, quantize, residual_autotune,
                        residual_score,
-                       residual_workspace_bytes, score, score_topk, score_topk_workspace_bytes,
+                       residual_workspace_bytes, score, score_topk, score_topk_noalloc,
+                       score_topk_workspace_bytes, NOALLOC_SCRATCH_BYTES,
                        score_unfused, stream_probe, lds_probe, topk,
                        topk_workspace_bytes, unfused_workspace_bytes, validate)

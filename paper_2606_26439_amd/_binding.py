@@ -81,6 +81,8 @@ def lib():
     L.maxsim_score_topk_workspace_size.restype = ctypes.c_size_t
     L.maxsim_score_topk.argtypes = [_P(CSR), _P(CSR), _P(Cand), ctypes.c_int32, _vp, _vp, _vp,
                                     ctypes.c_size_t, _vp]
+    L.maxsim_score_topk_noalloc.argtypes = [_P(CSR), _P(CSR), _P(Cand), ctypes.c_int32, _vp,
+                                            _vp, _vp]
     L.maxsim_score_unfused_workspace_size.argtypes = [_P(CSR), _P(CSR)]
     L.maxsim_score_unfused_workspace_size.restype = ctypes.c_size_t
     L.maxsim_score_unfused.argtypes = [_P(CSR), _P(CSR), _vp, _vp, ctypes.c_size_t, _vp]
@@ -113,7 +115,8 @@ def lib():
                                       _vp]
     L.maxsim_lds_probe.argtypes = [_vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _vp,
                                    ctypes.c_int64, _vp]
-    for name in ("maxsim_quantize", "maxsim_score", "maxsim_score_topk", "maxsim_score_unfused",
+    for name in ("maxsim_quantize", "maxsim_score", "maxsim_score_topk",
+                 "maxsim_score_topk_noalloc", "maxsim_score_unfused",
                  "maxsim_pq_score",
                  "maxsim_topk", "maxsim_autotune", "maxsim_pq_autotune",
                  "maxsim_load_tune_cache", "maxsim_stream_probe", "maxsim_lds_probe",
@@ -276,6 +279,29 @@ def score_topk(q: Tokens, d: Tokens, k: int, cand: Candidates = None, workspace=
                                    ctypes.byref(cc) if cc is not None else None, k,
                                    _ptr(out[0]), _ptr(out[1]), _ptr(workspace),
                                    workspace.numel(), _stream(stream)))
+    return out
+
+
+# Bytes of the library's fixed per-GPU scratch (include/maxsim.h,
+# MAXSIM_NOALLOC_SCRATCH_BYTES): the largest score_topk workspace that
+# score_topk_noalloc accepts.
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def score_topk_noalloc(q: Tokens, d: Tokens, k: int, cand: Candidates = None, out=None,
+                       stream=None):
+    """score_topk through the entry point that allocates nothing: its
+    workspace is the library's fixed per-GPU scratch (calls that overlap on
+    one GPU race). Only the outputs are allocated here, when `out` is None."""
+    dev = d.offsets.device
+    if out is None:
+        out = (torch.empty((q.n_sets, k), dtype=torch.float32, device=dev),
+               torch.empty((q.n_sets, k), dtype=torch.int32, device=dev))
+    qc, dc = q.csr(), d.csr()
+    cc = cand.c() if cand is not None else None
+    _check(lib().maxsim_score_topk_noalloc(ctypes.byref(qc), ctypes.byref(dc),
+                                           ctypes.byref(cc) if cc is not None else None, k,
+                                           _ptr(out[0]), _ptr(out[1]), _stream(stream)))
     return out
 
 

@@ -504,6 +504,43 @@ size_t maxsim_score_topk_workspace_size(const maxsim_csr* q, const maxsim_csr* d
   return st ? 0 : T.total;
 }
 
+namespace {
+
+// Enqueues a planned fused score + top-k (both launches) with the workspace
+// at ws (at least T.total bytes, 16-byte aligned).
+maxsim_status launch_score_topk(const FusedPlan& pl, FusedLaunch& L, const TopkLayout& T,
+                                int64_t n_q, int32_t k, float* out_scores, int32_t* out_ids,
+                                char* ws, hipStream_t s) {
+  if (L.grid > 0) {
+    FusedParams& P = L.P;
+    P.scores = nullptr;
+    P.wg_lo = (int64_t*)(ws + T.wg_lo);
+    P.part_cnt = (uint32_t*)(ws + T.cnt);
+    P.part_keys = (uint64_t*)(ws + T.keys);
+    P.key_spill = (uint32_t*)(ws + T.spill);
+    hipError_t e = L.fns.launch(P, (int)L.grid, L.lds, s);
+    if (e != hipSuccess) return hip_fail(e, "fused score_topk launch");
+  }
+  MergeParams M{};
+  M.cand_off = pl.P.cand_off;
+  M.n_q = n_q;
+  M.n_docs = pl.P.n_docs;
+  M.n_upairs = pl.P.n_upairs;
+  M.group = pl.P.group;
+  M.grid = (int32_t)L.grid;
+  M.k = k;
+  M.wg_lo = (const int64_t*)(ws + T.wg_lo);
+  M.part_keys = (const uint64_t*)(ws + T.keys);
+  M.part_cnt = (const uint32_t*)(ws + T.cnt);
+  M.out_scores = out_scores;
+  M.out_ids = out_ids;
+  hipError_t e = launch_topk_merge(M, s);
+  if (e != hipSuccess) return hip_fail(e, "top-k merge launch");
+  return MAXSIM_OK;
+}
+
+}  // namespace
+
 maxsim_status maxsim_score_topk(const maxsim_csr* queries, const maxsim_csr* docs,
                                 const maxsim_candidates* cand, int32_t k, float* out_scores,
                                 int32_t* out_ids, void* workspace, size_t ws_bytes,
@@ -519,34 +556,67 @@ maxsim_status maxsim_score_topk(const maxsim_csr* queries, const maxsim_csr* doc
     return fail(MAXSIM_EWORKSPACE, "score_topk: workspace needs %zu bytes", T.total);
   if (!aligned(workspace, 16))
     return fail(MAXSIM_EINVAL, "score_topk: workspace must be 16-byte aligned");
-  char* ws = (char*)workspace;
-  hipStream_t s = (hipStream_t)stream;
-  if (L.grid > 0) {
-    FusedParams& P = L.P;
-    P.scores = nullptr;
-    P.wg_lo = (int64_t*)(ws + T.wg_lo);
-    P.part_cnt = (uint32_t*)(ws + T.cnt);
-    P.part_keys = (uint64_t*)(ws + T.keys);
-    P.key_spill = (uint32_t*)(ws + T.spill);
-    hipError_t e = L.fns.launch(P, (int)L.grid, L.lds, s);
-    if (e != hipSuccess) return hip_fail(e, "fused score_topk launch");
+  return launch_score_topk(pl, L, T, queries->n_sets, k, out_scores, out_ids, (char*)workspace,
+                           (hipStream_t)stream);
+}
+
+// ------------------------------------------------- allocation-free top-k --
+// The workspace of maxsim_score_topk_noalloc: a file-scope device array, one
+// copy on every GPU the library runs on, held until the process ends. In host
+// code `scratch` names the symbol only, not device memory: its address on a
+// device comes from hipGetSymbolAddress with that device current, looked up
+// once per device and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[MAXSIM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// The current device's copy of `scratch` (no allocation: the array is part of
+// the library's code object on that device).
+maxsim_status scratch_on_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "score_topk_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+    return fail(MAXSIM_EUNSUPPORTED, "score_topk_noalloc: device %d beyond the first %d", dev,
+                SCRATCH_MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "score_topk_noalloc: scratch address lookup");
+    if (!p) return fail(MAXSIM_EHIP, "score_topk_noalloc: scratch address lookup gave NULL");
+    g_scratch_ptr[dev] = p;
   }
-  MergeParams M{};
-  M.cand_off = pl.P.cand_off;
-  M.n_q = queries->n_sets;
-  M.n_docs = pl.P.n_docs;
-  M.n_upairs = pl.P.n_upairs;
-  M.group = pl.P.group;
-  M.grid = (int32_t)L.grid;
-  M.k = k;
-  M.wg_lo = (const int64_t*)(ws + T.wg_lo);
-  M.part_keys = (const uint64_t*)(ws + T.keys);
-  M.part_cnt = (const uint32_t*)(ws + T.cnt);
-  M.out_scores = out_scores;
-  M.out_ids = out_ids;
-  hipError_t e = launch_topk_merge(M, s);
-  if (e != hipSuccess) return hip_fail(e, "top-k merge launch");
+  *out = g_scratch_ptr[dev];
   return MAXSIM_OK;
+}
+
+}  // namespace
+
+maxsim_status maxsim_score_topk_noalloc(const maxsim_csr* queries, const maxsim_csr* docs,
+                                        const maxsim_candidates* cand, int32_t k,
+                                        float* out_scores, int32_t* out_ids,
+                                        maxsim_stream_t stream) {
+  FusedPlan pl;
+  FusedLaunch L;
+  TopkLayout T;
+  maxsim_status st = plan_score_topk(queries, docs, cand, k, pl, L, T);
+  if (st) return st;
+  if (queries->n_sets == 0) return MAXSIM_OK;
+  if (!out_scores || !out_ids) return fail(MAXSIM_EINVAL, "score_topk_noalloc: NULL output");
+  if (T.total > (size_t)MAXSIM_NOALLOC_SCRATCH_BYTES)
+    return fail(MAXSIM_EWORKSPACE,
+                "score_topk_noalloc: this problem needs %zu bytes of workspace, above the fixed "
+                "%zu-byte scratch (use maxsim_score_topk with a caller workspace)",
+                T.total, (size_t)MAXSIM_NOALLOC_SCRATCH_BYTES);
+  void* p = nullptr;
+  if ((st = scratch_on_current_device(&p))) return st;
+  return launch_score_topk(pl, L, T, queries->n_sets, k, out_scores, out_ids, (char*)p,
+                           (hipStream_t)stream);
 }
 
 size_t maxsim_score_unfused_workspace_size(const maxsim_csr* q, const maxsim_csr* d) {
