@@ -686,8 +686,47 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
 
 // ---------------------------------------------------------------------------
 // Unfused comparator, step 1: S[a][t][n] = sum_k d_tk q_an (FP32, to HBM).
-// One wave per 16-row tile of the document tokens, Q staged in LDS as above.
+// Each wave takes every (grid waves)-th 16-row tile of the document tokens,
+// query a (blockIdx.y) staged in LDS, and writes the tile's 16 S rows with
+// non-temporal stores that cover whole rows.
 // ---------------------------------------------------------------------------
+// The comparator's query operand: block nb's MFMA column c holds query token
+// c * NQB + nb, so a lane's NQB accumulators of one S row are NQB adjacent
+// columns and one tile row is written by 16 lanes as one contiguous run.
+template <int NQB>
+__device__ void stage_query_interleaved(const FusedParams& P, int64_t a, u32x4* q_lds, int t0,
+                                        int nthreads) {
+  const int ncg = P.ncg;
+  const int total = NQB * ncg * 64;
+  const int64_t q0 = P.q_off[a];
+  const int nq = (int)(P.q_off[a + 1] - q0);
+  for (int idx = t0; idx < total; idx += nthreads) {
+    const int ln = idx & 63, rest = idx >> 6;
+    const int cg = rest % ncg, nb = rest / ncg;
+    const int tok = (ln & 15) * NQB + nb;
+    const int beta = cg * 4 + (ln >> 4);
+    u32x4 v = {0, 0, 0, 0};
+    if (tok < nq && beta * 16 < P.row_bytes)
+      v = *(const u32x4*)(P.q_tok + (q0 + tok) * P.row_bytes + beta * 16);
+    q_lds[idx] = v;
+  }
+}
+
+template <int N>
+struct f32vec;
+template <>
+struct f32vec<1> {
+  typedef float type;
+};
+template <>
+struct f32vec<2> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct f32vec<4> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+
 template <int DT, int NQB, int DCH, int NW>
 __global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, float* S) {
   extern __shared__ u32x4 q_lds[];
@@ -695,6 +734,7 @@ __global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, floa
   constexpr int CB = DCH * ESZ;
   constexpr int NL = CB / 64;
   constexpr int NQP = NQB * 16;
+  typedef typename f32vec<NQB>::type outv;
   const int lane = lane_id();
   const int r = lane & 15, g = lane >> 4;
   const int wave = uniform(threadIdx.x >> 6);
@@ -702,80 +742,142 @@ __global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, floa
   const int64_t T = P.tokens_per_query;
   const int64_t ntiles = (T + 15) / 16;
   const int ncg = P.ncg;
+  const int nch = P.nch;
 
-  stage_unit<NQB>(P, a, q_lds, threadIdx.x, NW * 64);  // group 1: unit a = query a
+  stage_query_interleaved<NQB>(P, a, q_lds, threadIdx.x, NW * 64);
   const int nq = uniform((int)(P.q_off[a + 1] - P.q_off[a]));
-  __syncthreads();
+  __syncthreads();  // the only barrier: every wave passes it before any exits
   int qsc[NQB];
 #pragma unroll
   for (int nb = 0; nb < NQB; ++nb) {
     qsc[nb] = 127;
     if constexpr (DT == DT_FP8) {
-      int row = nb * 16 + r;
-      if (row < nq) qsc[nb] = e8m0_of(P.q_scales[P.q_off[a] + row]);
+      const int tok = r * NQB + nb;
+      if (tok < nq) qsc[nb] = e8m0_of(P.q_scales[P.q_off[a] + tok]);
     }
   }
   float* Sa = S + a * T * NQP;
-  for (int64_t tile = (int64_t)blockIdx.x * NW + wave; tile < ntiles;
-       tile += (int64_t)gridDim.x * NW) {
-    int64_t row = tile * 16 + r;
+  const int64_t stride = (int64_t)gridDim.x * NW;
+  int64_t tile = (int64_t)blockIdx.x * NW + wave;
+  if (tile >= ntiles) return;
+
+  // one (tile, chunk) step of document rows: lane (r, g) takes row r of the
+  // tile (the last row repeated past T), 16 bytes per 64-byte column group;
+  // columns past d read the row's last 16 bytes (the query operand is zero
+  // there)
+  auto load = [&](int64_t tl, int ch, u32x4 (&bb)[NL], int& sc) {
+    int64_t row = tl * 16 + r;
     if (row > T - 1) row = T - 1;
-    int sc = 127;
-    if constexpr (DT == DT_FP8) sc = e8m0_of(P.d_scales[row]);
-    f32x4 acc[NQB];
+    const char* base = P.d_tok + row * P.row_bytes + ch * CB;
+    const int cmax = P.row_bytes - 16 - ch * CB;
 #pragma unroll
-    for (int nb = 0; nb < NQB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int chunk = 0; chunk < P.nch; ++chunk) {
-      u32x4 bb[NL];
-      // columns past d: the row's last 16 bytes (the query operand is zero there)
-      const char* base = P.d_tok + row * P.row_bytes + chunk * CB;
-      const int cmax = P.row_bytes - 16 - chunk * CB;
-#pragma unroll
-      for (int c = 0; c < NL; ++c) {
-        const int col = c * 64 + g * 16;
-        bb[c] = *(const u32x4*)(base + (col < cmax ? col : cmax));
-      }
-#pragma unroll
-      for (int nb = 0; nb < NQB; ++nb) {
-        u32x4 qb[NL];
-#pragma unroll
-        for (int c = 0; c < NL; ++c) qb[c] = q_lds[(nb * ncg + chunk * NL + c) * 64 + lane];
-        acc[nb] = mma_step<DT, NL>(acc[nb], bb, qb, sc, qsc[nb]);
-      }
+    for (int c = 0; c < NL; ++c) {
+      const int col = c * 64 + g * 16;
+      bb[c] = *(const u32x4*)(base + (col < cmax ? col : cmax));
     }
-    // lane holds S rows 4g..4g+3 of column nb*16 + r
+    if constexpr (DT == DT_FP8) sc = e8m0_of(P.d_scales[row]);
+  };
+
+  // software pipeline over the wave's steps: the next step's rows are in
+  // flight while the current step's MFMAs run
+  u32x4 nxt[NL];
+  int nsc = 127;
+  load(tile, 0, nxt, nsc);
+  int ch = 0;
+  f32x4 acc[NQB];
+#pragma unroll
+  for (int nb = 0; nb < NQB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  while (true) {
+    u32x4 cur[NL];
+#pragma unroll
+    for (int c = 0; c < NL; ++c) cur[c] = nxt[c];
+    const int sc = nsc;
+    int ch2 = ch + 1;
+    int64_t tile2 = tile;
+    if (ch2 == nch) {
+      ch2 = 0;
+      tile2 = tile + stride;
+    }
+    const bool more = tile2 < ntiles;
+    if (more) load(tile2, ch2, nxt, nsc);
 #pragma unroll
     for (int nb = 0; nb < NQB; ++nb) {
+      u32x4 qb[NL];
+#pragma unroll
+      for (int c = 0; c < NL; ++c) qb[c] = q_lds[(nb * ncg + ch * NL + c) * 64 + lane];
+      acc[nb] = mma_step<DT, NL>(acc[nb], cur, qb, sc, qsc[nb]);
+    }
+    if (ch == nch - 1) {
+      // lane (r, g) holds S rows 4g..4g+3, columns r*NQB .. r*NQB + NQB - 1:
+      // one non-temporal store per row, the 16 lanes of a row writing its
+      // NQP columns contiguously
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        int64_t orow = tile * 16 + 4 * g + i;
-        if (orow < T) Sa[orow * NQP + nb * 16 + r] = acc[nb][i];
+        const int64_t orow = tile * 16 + 4 * g + i;
+        outv v;
+        if constexpr (NQB == 1) {
+          v = acc[0][i];
+        } else {
+#pragma unroll
+          for (int nb = 0; nb < NQB; ++nb) v[nb] = acc[nb][i];
+        }
+        if (orow < T) __builtin_nontemporal_store(v, (outv*)(Sa + orow * NQP + r * NQB));
       }
+#pragma unroll
+      for (int nb = 0; nb < NQB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
+    if (!more) break;
+    tile = tile2;
+    ch = ch2;
   }
 }
 
 // Unfused comparator, step 2: read S back, max over each document's rows,
-// sum over the query tokens. One wave per (query, doc) pair.
+// sum over the query tokens. One wave per (query, doc) pair: the document's
+// rows of S are one contiguous block, read with 16-byte non-temporal loads
+// (lane l: row l / LPR of each group of RPL rows, columns 4 (l % LPR) ..
+// + 3), U loads in flight; rows past the document's end repeat its last row.
 template <int NQP>
 __global__ __launch_bounds__(256) void seg_maxsum_kernel(FusedParams P, const float* S) {
-  constexpr int RPI = 64 / NQP;  // rows per iteration
+  constexpr int LPR = NQP / 4;   // lanes per S row
+  constexpr int RPL = 64 / LPR;  // rows per wave load
+  constexpr int U = 4;           // loads in flight per lane
   const int lane = lane_id();
-  const int col = lane % NQP, rsub = lane / NQP;
+  const int cg = lane % LPR, rsub = lane / LPR;
   const int64_t T = P.tokens_per_query;
   const int64_t nw = (int64_t)gridDim.x * 4;
   for (int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); p < P.n_pairs; p += nw) {
-    int64_t a = p / P.n_docs, b = p - a * P.n_docs;
-    int nq = (int)(P.q_off[a + 1] - P.q_off[a]);
-    int64_t t0 = P.d_off[b], t1 = P.d_off[b + 1];
-    const float* Sa = S + a * T * NQP;
-    float m = -__builtin_inff();
-    for (int64_t t = t0 + rsub; t < t1; t += RPI) m = fmaxf(m, Sa[t * NQP + col]);
+    const int64_t a = p / P.n_docs, b = p - a * P.n_docs;
+    const int nq = (int)(P.q_off[a + 1] - P.q_off[a]);
+    const int64_t t0 = P.d_off[b], t1 = P.d_off[b + 1];
+    const f32x4* Sa = (const f32x4*)(S + a * T * NQP);
+    f32x4 m = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+    for (int64_t t = t0; t < t1; t += RPL * U) {
+      f32x4 v[U];
 #pragma unroll
-    for (int off = NQP; off < 64; off <<= 1) m = fmaxf(m, xor_shfl(m, off));
-    float v = (col < NQP) ? m : 0.f;
+      for (int u = 0; u < U; ++u) {
+        int64_t tt = t + u * RPL + rsub;
+        tt = tt < t1 ? tt : t1 - 1;
+        v[u] = __builtin_nontemporal_load(Sa + tt * LPR + cg);
+      }
 #pragma unroll
-    for (int off = NQP / 2; off >= 1; off >>= 1) v += xor_shfl(v, off);
+      for (int u = 0; u < U; ++u) {
+        m.x = fmaxf(m.x, v[u].x);
+        m.y = fmaxf(m.y, v[u].y);
+        m.z = fmaxf(m.z, v[u].z);
+        m.w = fmaxf(m.w, v[u].w);
+      }
+    }
+#pragma unroll
+    for (int off = LPR; off < 64; off <<= 1) {
+      m.x = fmaxf(m.x, xor_shfl(m.x, off));
+      m.y = fmaxf(m.y, xor_shfl(m.y, off));
+      m.z = fmaxf(m.z, xor_shfl(m.z, off));
+      m.w = fmaxf(m.w, xor_shfl(m.w, off));
+    }
+    float v = (m.x + m.y) + (m.z + m.w);
+#pragma unroll
+    for (int off = LPR / 2; off >= 1; off >>= 1) v += xor_shfl(v, off);
     if (lane == 0) P.scores[p] = (nq == 0) ? 0.f : (t1 == t0 ? -__builtin_inff() : v);
   }
 }

@@ -87,6 +87,14 @@ def fused_bytes(n_tokens, n_docs, n_pairs, nq_tokens_total, dim, dtype, with_ind
     return b
 
 
+def fused_topk_bytes(n_tokens, n_docs, n_queries, nq_tokens_total, dim, dtype, k):
+    """Fused scoring with the top-k selected in the scorer: the same reads,
+    but the output is k (score, id) pairs per query instead of one score per
+    (query, doc) pair."""
+    b = fused_bytes(n_tokens, n_docs, 0, nq_tokens_total, dim, dtype)
+    return b + 8 * k * n_queries
+
+
 def unfused_bytes(n_tokens, n_docs, n_pairs, nq, dim, dtype):
     """Fused bytes plus writing and reading back S [T, Nq] in FP32."""
     return fused_bytes(n_tokens, n_docs, n_pairs, nq, dim, dtype) + 2 * n_tokens * nq * 4

@@ -3,8 +3,9 @@
 Requests (a query's token vectors plus a candidate id list) arrive at any
 time. The scheduler admits queued requests into the next batch whenever an
 execution slot is free and the batch's device memory fits the budget; a
-batch is one multi-query launch of the fused scorer (or the fused PQ scorer,
-or the residual-compressed scorer) followed by per-request top-k, enqueued on its own HIP stream, so batches
+batch is one multi-query call of the fused scorer with the per-request top-k
+selected in its epilogue (or the fused PQ scorer, or the residual-compressed
+scorer, followed by the per-request top-k), enqueued on its own HIP stream, so batches
 formed while earlier ones are still on the GPU overlap with them. Every score
 is produced by one wavefront with a fixed reduction order, so a request's
 result does not depend on which batch carried it.
@@ -79,8 +80,11 @@ class Scheduler:
     def __init__(self, dim: int, k: int = 100, max_inflight: int = 2,
                  mem_budget: int = 4 << 30, max_batch_requests: int = 64,
                  max_batch_pairs: int = 4_000_000, max_queue: int = 100_000,
-                 residual_centroids: int = 0):
+                 residual_centroids: int = 0, batch_overhead: int = 0):
         self.dim, self.k = dim, k
+        # device bytes a batch holds beyond what its requests are charged
+        # (GpuBackend.batch_overhead: the fused top-k's per-workgroup parts)
+        self.batch_overhead = batch_overhead
         self.topk_ws = topk_workspace_per_request(k)
         # a residual-mode request also holds its columns of the centroid-query
         # table: up to 64 (the query-token bound) FP32 entries per centroid
@@ -103,7 +107,8 @@ class Scheduler:
 
     def submit(self, r: Request) -> bool:
         """Queues a request; rejects one that can never fit or a full queue."""
-        if self.cost(r) > self.mem_budget or len(r.cand_ids) > self.max_batch_pairs:
+        if (self.cost(r) + self.batch_overhead > self.mem_budget
+                or len(r.cand_ids) > self.max_batch_pairs):
             r.status, r.error = "rejected", "request exceeds the device memory budget"
             return False
         if len(self.queue) >= self.max_queue:
@@ -140,7 +145,7 @@ class Scheduler:
             return None
         mode = self.queue[0].mode
         picked, nbytes, pairs = [], 0, 0
-        free = self.mem_budget - self.mem_in_use
+        free = self.mem_budget - self.mem_in_use - self.batch_overhead
         while self.queue and len(picked) < self.max_batch_requests:
             r = self.queue[0]
             if r.mode != mode:
@@ -153,6 +158,7 @@ class Scheduler:
             pairs += len(r.cand_ids)
         if not picked:
             return None
+        nbytes += self.batch_overhead
         b = Batch(self._next_bid, picked, mode, nbytes)
         self._next_bid += 1
         for r in picked:
@@ -186,14 +192,16 @@ class Backend:
 
 
 class GpuBackend(Backend):
-    """Launches a batch as one fused scoring call and one top-k call on a
-    stream of its own; completion is an event poll.
+    """Launches a batch on a stream of its own; completion is an event poll.
+    Exact batches are one fused score + top-k call (the per-request top-k
+    selected in the scorer's epilogue, no score array); PQ and residual
+    batches are one scoring call and one top-k call.
 
     Each in-flight slot owns a stream, a pinned host staging buffer and a
     device input buffer (grown on demand, then reused), so a batch costs one
     packed host-to-device copy, the conversion of its query tokens, the
-    scoring launch, the top-k launches and one device-to-host copy of the
-    top-k rows."""
+    scoring (and top-k) launches and one device-to-host copy of the top-k
+    rows."""
 
     def __init__(self, pool_docs, pool_pq=None, k: int = 100, n_slots: int = 3,
                  device: str = "cuda", pool_res=None):
@@ -204,6 +212,30 @@ class GpuBackend(Backend):
         self.res = pool_res
         self.slots = [dict(stream=torch.cuda.Stream(device=device), busy=False, cap=0)
                       for _ in range(n_slots)]
+
+    def batch_overhead(self, max_requests: int = 64, max_pairs: int = 4_000_000) -> int:
+        """Device bytes an exact batch holds beyond its requests' charge: the
+        fused score + top-k workspace of the largest batch the scheduler can
+        form (as the library sizes it, for every query-length class), less
+        the 4 bytes per (query, candidate) pair each request is already
+        charged for its scores (the call's key spill takes their place).
+        A host-side size query: the descriptors carry no device data."""
+        import ctypes
+        B = self.B
+        dt = self.docs.dtype
+        worst = 0
+        for max_len in (16, 32, 64):
+            qc = B.CSR(B.DTYPES[dt], self.docs.dim, max_requests, max_requests * max_len,
+                       max_len, 0, 16, 16, 16 if dt == "fp8" else None)
+            dc = self.docs.csr()
+            cc = B.Cand(16, 16, max_pairs)
+            n = int(B.lib().maxsim_score_topk_workspace_size(
+                ctypes.byref(qc), ctypes.byref(dc), ctypes.byref(cc), self.k))
+            if n == 0:
+                raise RuntimeError("score_topk workspace size query failed: "
+                                   + B.lib().maxsim_last_error().decode())
+            worst = max(worst, n)
+        return max(0, worst - 4 * max_pairs)
 
     def _slot(self):
         for sl in self.slots:
@@ -282,8 +314,10 @@ class GpuBackend(Backend):
             else:
                 qt, qs = B.quantize(q32, self.docs.dtype, stream=s)
                 Q = B.Tokens(qt, qoff, self.docs.dtype, qs, max_len=int(nq.max()))
-                scores = B.score(Q, self.docs, cand, stream=s)
-            ts, ti = B.topk(scores, coff, self.k, ids=ids, n_total=tc, stream=s)
+                scores = None
+                ts, ti = B.score_topk(Q, self.docs, self.k, cand, stream=s)
+            if scores is not None:
+                ts, ti = B.topk(scores, coff, self.k, ids=ids, n_total=tc, stream=s)
             sl["out_s"][:n].copy_(ts, non_blocking=True)
             sl["out_i"][:n].copy_(ti, non_blocking=True)
             ev = torch.cuda.Event()
