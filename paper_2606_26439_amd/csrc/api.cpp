@@ -647,9 +647,8 @@ maxsim_status maxsim_score_unfused(const maxsim_csr* queries, const maxsim_csr* 
   if (pl.n_pairs == 0) return MAXSIM_OK;
   if (queries->n_sets > 65535) return fail(MAXSIM_EUNSUPPORTED, "unfused: at most 65535 queries");
   DevInfo di = device_info();
-  int64_t tiles = (docs->n_tokens + 15) / 16;
-  int64_t grid = std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, (int64_t)di.cus * 8));
-  hipError_t e = launch_unfused(pl.dt, pl.nqb, pl.dch, pl.P, (float*)workspace, (int)grid, pl.lds,
+  // the launcher sizes the grid from the CU count and the kernel's occupancy
+  hipError_t e = launch_unfused(pl.dt, pl.nqb, pl.dch, pl.P, (float*)workspace, di.cus, pl.lds,
                                 (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "unfused launch");
   return MAXSIM_OK;

@@ -20,12 +20,12 @@ FusedFns fused_kernel_fns(int dt, int nqb, int dch, int pf, int nw, int qm, bool
   }
 }
 
-hipError_t launch_unfused(int dt, int nqb, int dch, const FusedParams& P, float* S, int grid,
+hipError_t launch_unfused(int dt, int nqb, int dch, const FusedParams& P, float* S, int cus,
                           size_t lds, hipStream_t s) {
   switch (dt) {
-    case 0: return launch_unfused_0(nqb, dch, P, S, grid, lds, s);
-    case 1: return launch_unfused_1(nqb, dch, P, S, grid, lds, s);
-    case 2: return launch_unfused_2(nqb, dch, P, S, grid, lds, s);
-    default: return launch_unfused_3(nqb, dch, P, S, grid, lds, s);
+    case 0: return launch_unfused_0(nqb, dch, P, S, cus, lds, s);
+    case 1: return launch_unfused_1(nqb, dch, P, S, cus, lds, s);
+    case 2: return launch_unfused_2(nqb, dch, P, S, cus, lds, s);
+    default: return launch_unfused_3(nqb, dch, P, S, cus, lds, s);
   }
 }

@@ -164,8 +164,9 @@ constexpr int lgkmcnt0_imm() { return 0xF | (0x3 << 14) | (0x7 << 4); }
 
 // Fused top-k, after every wave of the workgroup has stored its keys: for
 // each query with work pairs in the workgroup's range, the k best ranking keys
-// of those pairs (exact radix select over the wave key slots, or the spill
-// array for a wave whose range did not fit them) go to the query's part slot.
+// of those pairs (exact radix select over the workgroup's contiguous key
+// array, or over the wave key slots and the spill array for waves whose
+// ranges did not fit them) go to the query's part slot.
 // ranges[w], ranges[NW + w]: first and end work pair of wave w (contiguous).
 template <int NW>
 __device__ void topk_epilogue(const FusedParams& P, u32x4* lds, const int64_t* ranges) {
@@ -179,6 +180,8 @@ __device__ void topk_epilogue(const FusedParams& P, u32x4* lds, const int64_t* r
   if (threadIdx.x == 0) P.wg_lo[blockIdx.x] = lo;
   if (lo >= hi) return;
   const bool dense = P.cand_off == nullptr;
+  // keys in one contiguous array from the first pair (as the scorer stored them)
+  const bool contig = (hi - lo) * G <= P.key_cap;
   int64_t a0, a1;  // units with pairs in [lo, hi)
   if (dense) {
     a0 = lo / P.n_docs;
@@ -196,6 +199,8 @@ __device__ void topk_epilogue(const FusedParams& P, u32x4* lds, const int64_t* r
       if (a * G + gq >= P.n_q) break;
       auto get = [&](int64_t i) -> uint64_t {
         const int64_t p = p0 + i;
+        const uint32_t id = dense ? (uint32_t)(p - s0) : (uint32_t)P.cand_ids[p];
+        if (contig) return rank_key(lkeys[(p - lo) * G + gq], id);
         int w = 0;  // the wave whose range holds p: the last one starting at or before it
 #pragma unroll
         for (int v = 1; v < NW; ++v)
@@ -203,7 +208,6 @@ __device__ void topk_epilogue(const FusedParams& P, u32x4* lds, const int64_t* r
         const int64_t wl = ranges[w], wh = ranges[NW + w];
         const uint32_t key = (wh - wl) * G <= key_slots ? lkeys[w * key_slots + (p - wl) * G + gq]
                                                         : P.key_spill[p * G + gq];
-        const uint32_t id = dense ? (uint32_t)(p - s0) : (uint32_t)P.cand_ids[p];
         return rank_key(key, id);
       };
       const int64_t slot = ((int64_t)blockIdx.x + a) * G + gq;
@@ -265,10 +269,28 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
   const int64_t pe = PERWAVE ? my_hi : uniform64(wave_range_begin(P, wg0 + NW, W));
   // this wave's query operand in LDS (shared: the workgroup's copy)
   u32x4* qw = q_lds + (QM == Q_WAVE ? (size_t)wave * NQB * ncg * 64 : 0);
-  // fused top-k: this wave's key slots, used when its whole range fits them
+  // fused top-k: when the workgroup's whole range fits the LDS key slots,
+  // one contiguous array indexed from its first pair (the selection then
+  // reads keys by position); else this wave's share of the slots when its
+  // range fits them, else the spill array
   const int key_slots = P.key_cap / NW;
   const bool keys_in_lds = (my_hi - my_lo) * P.group <= key_slots;
-  uint32_t* const wave_keys = (uint32_t*)((char*)q_lds + P.lds_keys_off) + wave * key_slots;
+  uint32_t* const wg_keys = (uint32_t*)((char*)q_lds + P.lds_keys_off);
+  uint32_t* const wave_keys = wg_keys + wave * key_slots;
+  // the wave ranges, published next to the key slots (read by the
+  // selection at the end as well)
+  int64_t* const ranges = (int64_t*)((char*)q_lds + P.lds_keys_off + (size_t)P.key_cap * 4);
+  int64_t wg_lo = 0;
+  bool keys_contig = false;
+  if (P.topk_k > 0) {
+    if (lane == 0) {
+      ranges[wave] = my_lo;
+      ranges[NW + wave] = my_hi;
+    }
+    __syncthreads();
+    wg_lo = uniform64(ranges[0]);
+    keys_contig = (uniform64(ranges[2 * NW - 1]) - wg_lo) * P.group <= P.key_cap;
+  }
 
   while (pb < pe) {
     int64_t a, qend;  // a: the unit (with candidate lists: the query)
@@ -352,7 +374,9 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       if ((qmask >> (16 + gq)) & 1u) v = __builtin_bit_cast(float, 0x7fc00000u);
       if (P.topk_k > 0) {
         const uint32_t key = topk_detail::score_key(v);
-        if (keys_in_lds)
+        if (keys_contig)
+          wg_keys[(pp - wg_lo) * P.group + gq] = key;
+        else if (keys_in_lds)
           wave_keys[(pp - my_lo) * P.group + gq] = key;
         else
           P.key_spill[pp * P.group + gq] = key;
@@ -672,13 +696,8 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
   }
 
   if (P.topk_k > 0) {
-    // publish the wave ranges next to the key slots; once every wave is done
-    // the query operand and ring area is free for the selection
-    int64_t* ranges = (int64_t*)((char*)q_lds + P.lds_keys_off + (size_t)P.key_cap * 4);
-    if (lane == 0) {
-      ranges[wave] = my_lo;
-      ranges[NW + wave] = my_hi;
-    }
+    // once every wave is done the query operand and ring area is free for
+    // the selection
     __syncthreads();
     topk_epilogue<NW>(P, q_lds, ranges);
   }
@@ -686,8 +705,9 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
 
 // ---------------------------------------------------------------------------
 // Unfused comparator, step 1: S[a][t][n] = sum_k d_tk q_an (FP32, to HBM).
-// Each wave takes every (grid waves)-th 16-row tile of the document tokens,
-// query a (blockIdx.y) staged in LDS, and writes the tile's 16 S rows with
+// Each wave takes a contiguous run of 16-row tiles of the document tokens,
+// streams them through an LDS ring as the fused scorer does, contracts them
+// with query a (blockIdx.y, staged in LDS) and writes the tiles' S rows with
 // non-temporal stores that cover whole rows.
 // ---------------------------------------------------------------------------
 // The comparator's query operand: block nb's MFMA column c holds query token
@@ -727,13 +747,20 @@ struct f32vec<4> {
   typedef float type __attribute__((ext_vector_type(4)));
 };
 
-template <int DT, int NQB, int DCH, int NW>
+template <int DT, int NQB, int DCH, int NW, int PF>
 __global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, float* S) {
   extern __shared__ u32x4 q_lds[];
   constexpr int ESZ = elem_size<DT>::value;
-  constexpr int CB = DCH * ESZ;
-  constexpr int NL = CB / 64;
+  constexpr int CB = DCH * ESZ;  // bytes of one row within one chunk
+  constexpr int NL = CB / 64;    // 16-byte operand reads per lane per step
   constexpr int NQP = NQB * 16;
+  constexpr int TILE = 16 * CB;
+  constexpr int CPR = CB / 16;             // 16-byte pieces per tile row
+  constexpr int SW = CPR < 16 ? CPR : 16;  // XOR width
+  constexpr int SWD = 16 / SW;             // rows sharing a bank-group offset
+  constexpr int NLS = TILE / 1024;         // LDS-DMA instructions per step
+  constexpr int LOADS_PER_FILL = NLS + (DT == DT_FP8 ? 1 : 0);
+  static_assert(TILE % 1024 == 0, "a step is whole 1 KiB DMA rounds");
   typedef typename f32vec<NQB>::type outv;
   const int lane = lane_id();
   const int r = lane & 15, g = lane >> 4;
@@ -757,60 +784,87 @@ __global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, floa
     }
   }
   float* Sa = S + a * T * NQP;
-  const int64_t stride = (int64_t)gridDim.x * NW;
-  int64_t tile = (int64_t)blockIdx.x * NW + wave;
-  if (tile >= ntiles) return;
+  // this wave's contiguous share of the tiles
+  const int64_t W = (int64_t)gridDim.x * NW, w = (int64_t)blockIdx.x * NW + wave;
+  const int64_t tile_lo = (ntiles / W) * w + ((ntiles % W) * w) / W;
+  const int64_t tile_hi = (ntiles / W) * (w + 1) + ((ntiles % W) * (w + 1)) / W;
+  if (tile_lo >= tile_hi) return;
 
-  // one (tile, chunk) step of document rows: lane (r, g) takes row r of the
-  // tile (the last row repeated past T), 16 bytes per 64-byte column group;
-  // columns past d read the row's last 16 bytes (the query operand is zero
-  // there)
-  auto load = [&](int64_t tl, int ch, u32x4 (&bb)[NL], int& sc) {
-    int64_t row = tl * 16 + r;
-    if (row > T - 1) row = T - 1;
-    const char* base = P.d_tok + row * P.row_bytes + ch * CB;
-    const int cmax = P.row_bytes - 16 - ch * CB;
-#pragma unroll
-    for (int c = 0; c < NL; ++c) {
-      const int col = c * 64 + g * 16;
-      bb[c] = *(const u32x4*)(base + (col < cmax ? col : cmax));
+  // Each (tile, chunk) step arrives in a per-wave LDS ring by non-temporal
+  // global_load_lds (1 KiB of consecutive row bytes per instruction); piece
+  // p of tile row rho lands at rho * CPR + (p ^ swz(rho)), so the operand
+  // reads (lane (r, g) takes row r) hit 16 different bank groups. Rows past
+  // T repeat row T - 1 and columns past d repeat the row's last 16 bytes
+  // (the query operand is zero there); rows past T are not stored.
+  char* ring = (char*)q_lds + (size_t)NQB * ncg * 1024 + (size_t)wave * PF * TILE;
+  auto swz = [](int row) { return (row / SWD) & (SW - 1); };
+  int64_t ct = tile_lo;  // fill cursor: tile and chunk
+  int cc = 0;
+  int64_t ftile[PF];
+  int fchunk[PF], fsc[PF];
+  bool flive[PF];
+  auto fill = [&](const int sl) {
+    const bool live = ct < tile_hi;
+    const char* tb = g_zero_row;
+    int lim = 0, cmax = CB;
+    if (live) {
+      tb = P.d_tok + ct * 16 * P.row_bytes + cc * CB;
+      const int64_t left = T - 1 - ct * 16;
+      lim = left < 15 ? (int)left : 15;
+      cmax = P.row_bytes - 16 - cc * CB;
     }
-    if constexpr (DT == DT_FP8) sc = e8m0_of(P.d_scales[row]);
+    char* slot = ring + sl * TILE;
+#pragma unroll
+    for (int i = 0; i < NLS; ++i) {
+      const int ch = 64 * i + lane;
+      const int rho = ch / CPR, p = ch % CPR;
+      const int col = (p ^ swz(rho)) * 16;
+      const unsigned off =
+          (unsigned)((rho < lim ? rho : lim) * P.row_bytes + (col < cmax ? col : cmax));
+      __builtin_amdgcn_global_load_lds((const void*)(tb + off),
+                                       (__attribute__((address_space(3))) void*)(slot + i * 1024),
+                                       16, 0, 2 /* non-temporal */);
+    }
+    if constexpr (DT == DT_FP8) {
+      const float* sp = (const float*)g_zero_row;
+      if (live) sp = P.d_scales + ct * 16 + (r < lim ? r : lim);
+      fsc[sl] = e8m0_of(*sp);
+    } else {
+      fsc[sl] = 127;
+    }
+    flive[sl] = live;
+    ftile[sl] = ct;
+    fchunk[sl] = cc;
+    if (live && ++cc == nch) {
+      cc = 0;
+      ++ct;
+    }
   };
 
-  // software pipeline over the wave's steps: the next step's rows are in
-  // flight while the current step's MFMAs run
-  u32x4 nxt[NL];
-  int nsc = 127;
-  load(tile, 0, nxt, nsc);
-  int ch = 0;
   f32x4 acc[NQB];
+  auto consume = [&](const int sl) {
+    // every later fill issued LOADS_PER_FILL vector memory operations
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm((PF - 1) * LOADS_PER_FILL));
+    if (!flive[sl]) return;
+    const char* slot = ring + sl * TILE;
+    const int ch = fchunk[sl];
+    u32x4 bb[NL];
 #pragma unroll
-  for (int nb = 0; nb < NQB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  while (true) {
-    u32x4 cur[NL];
-#pragma unroll
-    for (int c = 0; c < NL; ++c) cur[c] = nxt[c];
-    const int sc = nsc;
-    int ch2 = ch + 1;
-    int64_t tile2 = tile;
-    if (ch2 == nch) {
-      ch2 = 0;
-      tile2 = tile + stride;
-    }
-    const bool more = tile2 < ntiles;
-    if (more) load(tile2, ch2, nxt, nsc);
+    for (int c = 0; c < NL; ++c)
+      bb[c] = *(const u32x4*)(slot + (r * CPR + ((c * 4 + g) ^ swz(r))) * 16);
 #pragma unroll
     for (int nb = 0; nb < NQB; ++nb) {
       u32x4 qb[NL];
 #pragma unroll
       for (int c = 0; c < NL; ++c) qb[c] = q_lds[(nb * ncg + ch * NL + c) * 64 + lane];
-      acc[nb] = mma_step<DT, NL>(acc[nb], cur, qb, sc, qsc[nb]);
+      const f32x4 base = ch == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[nb];
+      acc[nb] = mma_step<DT, NL>(base, bb, qb, fsc[sl], qsc[nb]);
     }
     if (ch == nch - 1) {
       // lane (r, g) holds S rows 4g..4g+3, columns r*NQB .. r*NQB + NQB - 1:
       // one non-temporal store per row, the 16 lanes of a row writing its
       // NQP columns contiguously
+      const int64_t tile = ftile[sl];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t orow = tile * 16 + 4 * g + i;
@@ -823,13 +877,23 @@ __global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, floa
         }
         if (orow < T) __builtin_nontemporal_store(v, (outv*)(Sa + orow * NQP + r * NQB));
       }
-#pragma unroll
-      for (int nb = 0; nb < NQB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    if (!more) break;
-    tile = tile2;
-    ch = ch2;
+  };
+
+#pragma unroll
+  for (int sl = 0; sl < PF; ++sl) fill(sl);
+  while (true) {
+#pragma unroll
+    for (int sl = 0; sl < PF; ++sl) {
+      consume(sl);
+      fill(sl);
+    }
+    // slots are filled in order: a dead refill of slot 0 means every live
+    // slot has now been consumed
+    if (!flive[0]) break;
   }
+  // the idle refills target this wave's ring: let them land before exit
+  __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
 }
 
 // Unfused comparator, step 2: read S back, max over each document's rows,

@@ -106,16 +106,43 @@ FusedFns pick_dch(int dch, int pf, int nw, int qm, bool stage, int rt) {
   return pick_stage<NQB, 128>(pf, nw, qm, stage, rt);
 }
 
-template <int NQB, int DCH>
-hipError_t launch_unfused_t(const FusedParams& P, float* S, int grid, size_t lds, hipStream_t s) {
-  auto k1 = fused_detail::sim_matrix_kernel<DT, NQB, DCH, 4>;
+template <int NQB, int DCH, int NW, int PF>
+hipError_t launch_sim_matrix(const FusedParams& P, float* S, int cus, size_t lds, hipStream_t s) {
+  auto k1 = fused_detail::sim_matrix_kernel<DT, NQB, DCH, NW, PF>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k1,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k1, dim3(grid, (unsigned)P.n_q), dim3(256), lds, s, P, S);
-  hipError_t e = hipGetLastError();
+  int occ = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k1, NW * 64, lds);
+  if (e != hipSuccess) return e;
+  if (occ < 1) return hipErrorInvalidConfiguration;
+  // one resident wave per run of tiles: every workgroup starts at once
+  const int64_t tiles = (P.tokens_per_query + 15) / 16;
+  int64_t grid = (int64_t)occ * cus;
+  if (grid * NW > tiles) grid = (tiles + NW - 1) / NW;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k1, dim3((unsigned)grid, (unsigned)P.n_q), dim3(NW * 64), lds, s, P, S);
+  return hipGetLastError();
+}
+
+// Unfused comparator: S to HBM, then the segmented max / sum read back.
+// `lds` is the staged query's size; the LDS ring of the S kernel is added
+// here (4 waves with 3 steps in flight each, or 2 waves with 2 when that
+// does not fit beside a large query operand).
+template <int NQB, int DCH>
+hipError_t launch_unfused_t(const FusedParams& P, float* S, int cus, size_t lds, hipStream_t s) {
+  constexpr size_t LDS_MAX = 160 * 1024;  // gfx950 LDS per workgroup
+  const size_t big = lds + fused_detail::stage_ring_bytes<DT, DCH, 3, 4>();
+  const size_t small = lds + fused_detail::stage_ring_bytes<DT, DCH, 2, 2>();
+  hipError_t e;
+  if (big <= LDS_MAX)
+    e = launch_sim_matrix<NQB, DCH, 4, 3>(P, S, cus, big, s);
+  else if (small <= LDS_MAX)
+    e = launch_sim_matrix<NQB, DCH, 2, 2>(P, S, cus, small, s);
+  else
+    return hipErrorInvalidValue;
   if (e != hipSuccess) return e;
   constexpr int NQP = NQB * 16;
   int64_t blocks = (P.n_pairs + 3) / 4;
@@ -127,10 +154,10 @@ hipError_t launch_unfused_t(const FusedParams& P, float* S, int grid, size_t lds
 }
 
 template <int NQB>
-hipError_t unfused_dch(const FusedParams& P, float* S, int grid, size_t lds, int dch,
+hipError_t unfused_dch(const FusedParams& P, float* S, int cus, size_t lds, int dch,
                        hipStream_t s) {
-  return dch == 64 ? launch_unfused_t<NQB, 64>(P, S, grid, lds, s)
-                   : launch_unfused_t<NQB, 128>(P, S, grid, lds, s);
+  return dch == 64 ? launch_unfused_t<NQB, 64>(P, S, cus, lds, s)
+                   : launch_unfused_t<NQB, 128>(P, S, cus, lds, s);
 }
 
 }  // namespace
@@ -147,8 +174,8 @@ FusedFns CAT(fused_kernel_fns_, FUSED_DT)(int nqb, int dch, int pf, int nw, int 
 }
 
 hipError_t CAT(launch_unfused_, FUSED_DT)(int nqb, int dch, const FusedParams& P, float* S,
-                                           int grid, size_t lds, hipStream_t s) {
-  if (nqb == 1) return unfused_dch<1>(P, S, grid, lds, dch, s);
-  if (nqb == 2) return unfused_dch<2>(P, S, grid, lds, dch, s);
-  return unfused_dch<4>(P, S, grid, lds, dch, s);
+                                           int cus, size_t lds, hipStream_t s) {
+  if (nqb == 1) return unfused_dch<1>(P, S, cus, lds, dch, s);
+  if (nqb == 2) return unfused_dch<2>(P, S, cus, lds, dch, s);
+  return unfused_dch<4>(P, S, cus, lds, dch, s);
 }

@@ -36,9 +36,11 @@ struct FusedParams {
   int64_t n_units;   // ceil(n_q / group)
   int64_t n_upairs;  // work pairs: n_units * n_docs, or the candidate count
   // Fused top-k (topk_k > 0): a score is not stored; its ranking key goes to
-  // the key array of the wave that computed it (LDS, key_cap / NW slots per
-  // wave, at byte lds_keys_off of the dynamic LDS), or to key_spill[pair *
-  // group + query of the unit] when the wave's range does not fit; after its
+  // LDS at byte lds_keys_off of the dynamic LDS (key_cap slots): one array
+  // indexed from the workgroup's first pair when its whole range fits, else
+  // the slots of the wave that computed it (key_cap / NW per wave), or
+  // key_spill[pair * group + query of the unit] when the wave's range does
+  // not fit either; after its
   // waves finish, the workgroup writes the top-k keys of each query's part of
   // its range to slot (workgroup + unit) * group + query of part_keys (k keys)
   // and part_cnt, and its first work pair to wg_lo[workgroup].
@@ -93,7 +95,7 @@ struct FusedFns {
 // rt: document rows per step (16; 32 for FP8 with staged tiles and Q in VGPRs).
 FusedFns fused_kernel_fns(int dt, int nqb, int dch, int pf, int nw, int qm, bool stage, int rt);
 
-hipError_t launch_unfused(int dt, int nqb, int dch, const FusedParams& P, float* S, int grid,
+hipError_t launch_unfused(int dt, int nqb, int dch, const FusedParams& P, float* S, int cus,
                           size_t lds, hipStream_t s);
 
 // ---- PQ ----

@@ -7,9 +7,10 @@
 // 2^31, so ~id >= 2^31) and serves as padding that ranks below everything.
 //
 // block_topk() finds the k largest keys of n entries, enumerated by a
-// callable get(i), with a radix select: 12-bit digits from the top fix a key
-// prefix until the entries above the prefix plus the entries on it fit the
-// sort buffer; those are collected and sorted by a bitonic network. Integer
+// callable get(i), with a radix select: starting from the bits all keys
+// share, 12-bit digits fix a key prefix until the entries above the prefix
+// plus the entries on it fit the sort buffer; those are collected and sorted
+// by a bitonic network. Integer
 // keys only, so the result does not depend on the launch shape or on the
 // order in which entries are visited.
 #pragma once
@@ -122,19 +123,51 @@ __device__ int block_topk(int64_t n, int k, Get get, uint32_t* hist, uint64_t* b
     bitonic_desc(buf, p2);
     count = n < k ? (int)n : k;
   } else {
-    uint64_t prefix = 0;
-    int plen = 0;  // key bits fixed by the prefix
+    // The score bits every key shares (where the largest and the smallest
+    // score key agree) start the prefix, so the first digit already splits
+    // the keys: without this, keys of scores in a narrow range all fall into
+    // one or two bins of the top digit and their histogram atomics serialise.
+    uint32_t hmax = 0u, hmin = ~0u;
+    for (int64_t i = t; i < n; i += nt) {
+      const uint32_t h = (uint32_t)(get(i) >> 32);
+      hmax = h > hmax ? h : hmax;
+      hmin = h < hmin ? h : hmin;
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      const uint32_t a = (uint32_t)__shfl_xor((int)hmax, m, 64);
+      const uint32_t b = (uint32_t)__shfl_xor((int)hmin, m, 64);
+      hmax = a > hmax ? a : hmax;
+      hmin = b < hmin ? b : hmin;
+    }
+    // wave partials in the first 32 words of hist, before the bins are used
+    const int w = t >> 6, nw = nt >> 6;
+    if ((t & 63) == 0) {
+      hist[w] = hmax;
+      hist[16 + w] = hmin;
+    }
+    __syncthreads();
+    for (int i = 0; i < nw; ++i) {
+      hmax = hist[i] > hmax ? hist[i] : hmax;
+      hmin = hist[16 + i] < hmin ? hist[16 + i] : hmin;
+    }
+    __syncthreads();
+    int plen = hmax == hmin ? 32 : __builtin_clz(hmax ^ hmin);  // key bits fixed by the prefix
+    const uint64_t kmax = (uint64_t)hmax << 32;
+    uint64_t prefix = plen == 0 ? 0ull : kmax >> (64 - plen);
     uint32_t rem = (uint32_t)k, n_above = 0;
-    while (true) {
+    while (plen < 64) {
       const int dbits = 64 - plen < 12 ? 64 - plen : 12;
       const int shift = 64 - plen - dbits;
       const uint64_t dmask = (1ull << dbits) - 1ull;
+      // keys on the prefix: (key & pmask) == pbits (no shift by 64)
+      const uint64_t pmask = plen == 0 ? 0ull : ~0ull << (64 - plen);
+      const uint64_t pbits = plen == 0 ? 0ull : prefix << (64 - plen);
       for (int i = t; i < SEL_BINS; i += nt) hist[i] = 0u;
       __syncthreads();
       for (int64_t i = t; i < n; i += nt) {
         const uint64_t key = get(i);
-        if (plen == 0 || (key >> (64 - plen)) == prefix)
-          atomicAdd(&hist[(key >> shift) & dmask], 1u);
+        if ((key & pmask) == pbits) atomicAdd(&hist[(key >> shift) & dmask], 1u);
       }
       __syncthreads();
       uint32_t bin, above;
@@ -145,7 +178,7 @@ __device__ int block_topk(int64_t n, int k, Get get, uint32_t* hist, uint64_t* b
       rem -= above;
       prefix = (prefix << dbits) | bin;
       plen += dbits;
-      if (n_above + on_bin <= (uint32_t)cap || plen == 64) break;
+      if (n_above + on_bin <= (uint32_t)cap) break;
     }
     // entries above the prefix (n_above < k of them) go to the front, the
     // entries on it after them, as many as fit (past the last digit they are
@@ -155,13 +188,15 @@ __device__ int block_topk(int64_t n, int k, Get get, uint32_t* hist, uint64_t* b
       hist[SEL_BINS + 3] = 0u;
     }
     __syncthreads();
-    const int tail = 64 - plen;
+    // the prefix and each key's top plen bits, aligned at the top
+    const uint64_t tmask = plen == 64 ? ~0ull : ~(~0ull >> plen);
+    const uint64_t pbits = plen == 64 ? prefix : prefix << (64 - plen);
     for (int64_t i = t; i < n; i += nt) {
       const uint64_t key = get(i);
-      const uint64_t top = tail == 0 ? key : key >> tail;
-      if (top > prefix) {
+      const uint64_t top = key & tmask;
+      if (top > pbits) {
         buf[atomicAdd(&hist[SEL_BINS + 2], 1u)] = key;
-      } else if (top == prefix) {
+      } else if (top == pbits) {
         const uint32_t s = atomicAdd(&hist[SEL_BINS + 3], 1u);
         if (n_above + s < (uint32_t)cap) buf[n_above + s] = key;
       }

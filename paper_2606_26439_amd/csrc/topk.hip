@@ -322,6 +322,7 @@ namespace {
 
 constexpr int MERGE_THREADS = 1024;
 constexpr int MERGE_CAP = 2048;  // sort buffer: >= 2 * max k
+static_assert(MERGE_MAX_GRID % MERGE_THREADS == 0, "extras per thread");
 
 __global__ __launch_bounds__(MERGE_THREADS) void topk_merge_kernel(MergeParams M) {
   using namespace topk_detail;
@@ -345,28 +346,82 @@ __global__ __launch_bounds__(MERGE_THREADS) void topk_merge_kernel(MergeParams M
     return;
   }
   auto R = [&](int64_t b) -> int64_t { return b >= M.grid ? M.n_upairs : M.wg_lo[b]; };
-  // the last workgroup b < grid with R(b) <= x
-  auto last_at_or_before = [&](int64_t x) -> int64_t {
-    int64_t lo = 0, hi = M.grid - 1;  // R(0) = 0 <= x
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (R(mid) <= x) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-  };
-  const int64_t b0 = last_at_or_before(ps), b1 = last_at_or_before(pe - 1);
-  const int nb = (int)(b1 - b0 + 1);
-  for (int i = threadIdx.x; i < nb; i += MERGE_THREADS) {
-    const int64_t b = b0 + i;
-    cnts[i] = R(b) < R(b + 1) ? M.part_cnt[(b + a) * G + gq] : 0u;
+  // One round of loads for every workgroup b of the scoring launch: its
+  // first work pair (for b0, the last workgroup with R(b) <= ps, and b1, the
+  // last with R(b) <= pe - 1: R is non-decreasing with R(0) = 0, so each is a
+  // count minus one) and the size of its part for this query (0 when it
+  // scored nothing).
+  if (threadIdx.x < 2) hist[threadIdx.x] = 0u;
+  __syncthreads();
+  uint32_t c0 = 0, c1 = 0;
+  for (int b = threadIdx.x; b < M.grid; b += MERGE_THREADS) {
+    const int64_t r = R(b), r1 = R(b + 1);
+    const uint32_t c = M.part_cnt[(b + a) * G + gq];
+    c0 += r <= ps ? 1u : 0u;
+    c1 += r <= pe - 1 ? 1u : 0u;
+    cnts[b] = r < r1 ? c : 0u;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    c0 += (uint32_t)__shfl_xor((int)c0, o, 64);
+    c1 += (uint32_t)__shfl_xor((int)c1, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&hist[0], c0);
+    atomicAdd(&hist[1], c1);
   }
   __syncthreads();
-  auto get = [&](int64_t i) -> uint64_t {
-    const int bi = (int)(i / k);
-    const int j = (int)(i - (int64_t)bi * k);
-    return (uint32_t)j < cnts[bi] ? M.part_keys[((b0 + bi + a) * G + gq) * k + j] : 0ull;
+  const int64_t b0 = (int64_t)hist[0] - 1, b1 = (int64_t)hist[1] - 1;
+  __syncthreads();
+  const int nb = (int)(b1 - b0 + 1);
+  auto part = [&](int bi) -> const uint64_t* {
+    return M.part_keys + ((b0 + bi + a) * G + gq) * (int64_t)k;
   };
-  block_topk((int64_t)nb * k, k, get, hist, buf, MERGE_CAP, buf);
+  auto cnt = [&](int bi) -> uint32_t { return cnts[b0 + bi]; };
+  // Fast path: the first m keys of every part (each part is sorted), sorted
+  // together; their top k is the answer when no part holds a key left out
+  // that could reach it, i.e. when every part with more than m keys has its
+  // (m+1)-th key below the k-th of the result. Each part holds about k / nb
+  // of the answer on average, so m of twice that plus two rarely misses (and
+  // a miss takes the exact path below).
+  int m = 2 * ((k + nb - 1) / nb) + 2;
+  m = m < k ? m : k;
+  m = m < MERGE_CAP / nb ? m : MERGE_CAP / nb;
+  bool done = false;
+  if (m >= 1 && m < k) {
+    int p2 = 64;
+    while (p2 < nb * m) p2 <<= 1;
+    for (int i = threadIdx.x; i < p2; i += MERGE_THREADS) {
+      const int bi = i / m, j = i - bi * m;
+      buf[i] = (i < nb * m && (uint32_t)j < cnt(bi)) ? part(bi)[j] : 0ull;
+    }
+    // the (m+1)-th key of the parts that have one, loaded in the same round
+    // (nb <= MERGE_MAX_GRID = 4 x MERGE_THREADS)
+    uint64_t ex[MERGE_MAX_GRID / MERGE_THREADS];
+#pragma unroll
+    for (int q = 0; q < MERGE_MAX_GRID / MERGE_THREADS; ++q) {
+      const int bi = threadIdx.x + q * MERGE_THREADS;
+      ex[q] = (bi < nb && cnt(bi) > (uint32_t)m) ? part(bi)[m] : 0ull;
+    }
+    __syncthreads();
+    bitonic_desc(buf, p2);
+    const uint64_t kth = buf[k - 1];  // 0: fewer than k keys gathered
+    int ok = 1;
+#pragma unroll
+    for (int q = 0; q < MERGE_MAX_GRID / MERGE_THREADS; ++q) {
+      const int bi = threadIdx.x + q * MERGE_THREADS;
+      if (bi < nb && cnt(bi) > (uint32_t)m && ex[q] >= kth) ok = 0;
+    }
+    done = __syncthreads_and(ok) != 0;
+  }
+  if (!done) {
+    auto get = [&](int64_t i) -> uint64_t {
+      const int bi = (int)(i / k);
+      const int j = (int)(i - (int64_t)bi * k);
+      return (uint32_t)j < cnt(bi) ? part(bi)[j] : 0ull;
+    };
+    block_topk((int64_t)nb * k, k, get, hist, buf, MERGE_CAP, buf);
+  }
   for (int i = threadIdx.x; i < k; i += MERGE_THREADS) {
     const uint64_t key = buf[i];
     os[i] = key == 0ull ? -__builtin_inff() : key_score((uint32_t)(key >> 32));

@@ -424,6 +424,35 @@ def test_pq_candidates(pq_variant):
     assert_close_o1(got, want, f"pq candidates {pq_variant}")
 
 
+@pytest.mark.parametrize("pq_variant", ["mfma"], indirect=True)
+@pytest.mark.parametrize("nd_max", [3, 40])
+def test_pq_packed_tiles_equal_per_document_tiles(pq_variant, nd_max):
+    # Scoring every document, the decode kernel packs 16-token tiles across
+    # document boundaries (several documents end inside one tile when they
+    # are this short, empty ones included); with candidate lists it tiles
+    # each document on its own. The same documents scored both ways give the
+    # same bits: each row's dot products are the same and maxima are exact.
+    g = W.rng(61 + nd_max)
+    n_docs = 3000
+    lens = g.integers(0, nd_max + 1, n_docs)
+    lens[:5] = 0
+    lens[-3:] = 0
+    d_off = W.offsets_from_lengths(lens)
+    codes = g.integers(0, 256, size=(int(d_off[-1]), 8), dtype=np.uint8)
+    cb = (g.standard_normal((8, 256, 16)) * 0.25).astype(np.float16)
+    q_off = W.offsets_from_lengths([32, 7, 0, 64, 20])
+    q = W.unit_tokens(int(q_off[-1]), 128, g).astype(np.float16)
+    Q, D = _pq_device(q, q_off, cb, codes, d_off)
+    n_q = len(q_off) - 1
+    dense = M.pq_score(Q, D).cpu().numpy()
+    c_off = np.arange(n_q + 1, dtype=np.int64) * n_docs
+    c_ids = np.tile(np.arange(n_docs, dtype=np.int32), n_q)
+    per_doc = M.pq_score(Q, D, M.Candidates(dev(c_off), dev(c_ids))).cpu().numpy()
+    assert np.array_equal(dense.view(np.uint32), per_doc.view(np.uint32))
+    want = oracle.pq_decode_score(q.astype(np.float64), q_off, codes, cb.astype(np.float64), d_off)
+    assert_close_o1(dense, want, f"pq packed nd<={nd_max}")
+
+
 @pytest.mark.parametrize("q_dtype,cb_dtype", [("f32", "f16"), ("f16", "f32"), ("f32", "f32")])
 def test_pq_fp32_queries_and_codebooks(q_dtype, cb_dtype):
     # FP32 inputs go through the table kernel (the decode kernel takes FP16)
