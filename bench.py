@@ -144,6 +144,19 @@ def time_fn(fn, steps, warmup):
     return float(np.median(ms)), float(ms.mean()), float(ms.std())
 
 
+def settle_launches(fn, seconds, at_least=10):
+    """Warm-up launch count: enough launches of fn to fill `seconds` (from one
+    timed launch), at least `at_least`."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    one = max(time.perf_counter() - t0, 1e-6)
+    return max(at_least, int(seconds / one) + 1)
+
+
 def oracle_sample(wl, dtype, got_scores, n_sample, seed=5, n_o2=20000):
     """FP64 oracle on a sample of docs: returns (docs/s on one core, seconds,
     max rel err vs O1 over the sample, O2 error stats on the first n_o2 sampled
@@ -258,14 +271,16 @@ def exact_topk(wl, f32_scores, k=100, margin=1e-3):
     return set(cand[order].tolist()), len(cand)
 
 
-def gen_docs(n_tokens, dim, dtype, seed, sample_rows=None):
+def gen_docs(n_tokens, dim, dtype, seed, sample_rows=None, out=None):
     """Document tokens of `dtype` built chunk by chunk on the device (FP32 draw,
     then the library's conversion), plus the FP32 source of `sample_rows`
-    (sorted row indices) for the oracle."""
+    (sorted row indices) for the oracle. `out`: a preallocated [n_tokens,
+    dim] tensor of that type to fill instead of a new one."""
     import torch
     import paper_2606_26439_amd as M
     import workloads as W
-    tok = torch.empty((n_tokens, dim), dtype=M._binding.TORCH_DTYPES[dtype], device="cuda")
+    tok = out if out is not None else torch.empty(
+        (n_tokens, dim), dtype=M._binding.TORCH_DTYPES[dtype], device="cuda")
     sc = torch.empty(n_tokens, dtype=torch.float32, device="cuda") if dtype == "fp8" else None
     keep = []
     rows = np.asarray(sample_rows if sample_rows is not None else [], np.int64)
@@ -549,21 +564,28 @@ def bench_dim_tiling(batch_sizes=(100_000, 250_000, 500_000), dims=(64, 256, 512
     import workloads as W
     from paper_2606_26439_amd import roofline as R
     out = []
+    # one arena for every cell (the largest one's tokens), so each cell reads
+    # memory mapped once at the start of the section rather than a fresh
+    # allocation after a dozen large ones were freed (measured a few percent
+    # slower that way than in a fresh process)
+    arena = torch.empty(max(batch_sizes) * nd * max(dims) * 2, dtype=torch.uint8, device="cuda")
     for B in batch_sizes:
         for d in dims:
             T = B * nd
             d_off_np = np.arange(B + 1, dtype=np.int64) * nd
             samp = np.sort(np.random.default_rng(11).choice(B, size=64, replace=False))
             rows = np.concatenate([np.arange(b * nd, (b + 1) * nd) for b in samp])
-            tok, _, f32 = gen_docs(T, d, "bf16", seed=3000 + d, sample_rows=rows)
+            tok, _, f32 = gen_docs(T, d, "bf16", seed=3000 + d, sample_rows=rows,
+                                   out=arena[:T * d * 2].view(torch.bfloat16).view(T, d))
             q = W.unit_tokens(nq, d, W.rng(1))
             qt, _ = M.quantize(torch.from_numpy(q).cuda(), "bf16")
             Q = M.Tokens(qt, torch.tensor([0, nq], device="cuda"), "bf16", None, max_len=nq)
             D = M.Tokens(tok, torch.from_numpy(d_off_np).cuda(), "bf16", None, max_len=nd)
             sc = torch.empty(B, dtype=torch.float32, device="cuda")
-            # 5 warm-up launches: the first launches after the data is written
-            # run slow
-            med, mean, std = time_fn(lambda: M.score(Q, D, out=sc), 20, 5)
+            # the first launches after tens of GB of data are written run
+            # slow: at least 0.3 s of untimed launches, then 30 timed ones
+            med, mean, std = time_fn(lambda: M.score(Q, D, out=sc), 30, settle_launches(
+                lambda: M.score(Q, D, out=sc), 0.3))
             b = R.fused_bytes(T, B, B, nq, d, "bf16")
             got = sc.cpu().numpy()[samp].astype(np.float64)
             qv, _ = oracle.exact_values(q, "bf16")
@@ -577,7 +599,8 @@ def bench_dim_tiling(batch_sizes=(100_000, 250_000, 500_000), dims=(64, 256, 512
                 f"{rec['hbm_frac'] * 100:.1f}% HBM, err {rel:.1e}")
             out.append(rec)
             del tok, D, sc
-            torch.cuda.empty_cache()
+    del arena
+    torch.cuda.empty_cache()
     return out
 
 

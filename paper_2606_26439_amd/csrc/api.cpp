@@ -196,7 +196,7 @@ maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_
   if (n_pairs > 0 && !scores && need_scores) return fail(MAXSIM_EINVAL, "scores is NULL");
   pl.dt = q->dtype;
   // d-chunk width: 128 (the paper's dimension tiling), 64 when d > 128 is not
-  // a multiple of 128, and 256 for 1- and 2-byte rows of d >= 512 (same k
+  // a multiple of 128, and 256 for 1- and 2-byte rows of d >= 256 (same k
   // order, so the same bits; each row read becomes 512 contiguous bytes). A d
   // that is not a multiple of the chunk is zero-extended to whole chunks
   // inside the kernel: the query operand's columns past d are zero and the
@@ -206,9 +206,11 @@ maxsim_status plan_fused(const maxsim_csr* q, const maxsim_csr* d, const maxsim_
     pl.dch = q->dim <= 64 ? 64 : 128;
   else
     pl.dch = (q->dim % 128 == 0) ? 128 : 64;
-  if (esize(q->dtype) <= 2 && q->dim >= 512 && q->dim % 256 == 0) pl.dch = 256;
+  if (esize(q->dtype) <= 2 && q->dim >= 256 && q->dim % 256 == 0) pl.dch = 256;
   const int nch = (q->dim + pl.dch - 1) / pl.dch;
-  pl.qreg = nch == 1;
+  // the query operand sits in VGPRs when d fits one chunk of at most 128
+  // (a 256-wide chunk's query blocks live in LDS)
+  pl.qreg = nch == 1 && pl.dch <= 128;
   // Query units: without candidate lists, queries are grouped so one read of
   // a document tile serves several of them (up to 8 blocks of 16 query tokens
   // in VGPRs for 1- and 2-byte types, 4 otherwise).
