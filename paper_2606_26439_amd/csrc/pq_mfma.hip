@@ -9,17 +9,14 @@
 // c*32 + g*8 .. +8 of token r, which sit inside one centroid (dsub >= 8), so
 // one ds_read_b128 fetches them. The decoded tile is then contracted with
 // the query tokens held in VGPRs (B operand), several queries per wave, so
-// one decode serves NQB x 16 query tokens. Running maxima stay in VGPRs; at
-// a document's end lane swaps finish the max over rows and DPP row rotations
-// sum a query's tokens. FP16 products are exact and accumulate in FP32.
+// one decode serves NQB x 16 query tokens. Running maxima stay in VGPRs; rows
+// past a document's end are clamped to its last token; at the document's
+// end two xor-shuffles finish the max over rows and four sum a query's
+// tokens. FP16 products are exact and accumulate in FP32.
 //
 // Work item = (doc chunk, group of queries). Without candidate lists a group
 // holds NQB / BPQ queries (BPQ = 16-column blocks per query, from the
-// query-length bound) and each wave walks a contiguous run of documents in
-// 16-token tiles packed across document boundaries (no clamped rows: every
-// MFMA row is a document token); with candidate lists a group is one query
-// and each candidate document is tiled on its own, its last tile's rows past
-// the document's end clamped to its last token.
+// query-length bound); with candidate lists a group is one query.
 #include "device_common.h"
 #include "kernels.h"
 
@@ -66,22 +63,15 @@ __device__ __forceinline__ float sum_row16(float v) {
 
 template <int M>
 struct PqCodes;
-// keep(v): an empty use of a ring slot's code registers at the end of its
-// step, so the register allocator does not lend them to the step's score
-// stores: a refill of registers that a pending store still reads would make
-// the compiler wait for every outstanding vector memory operation (stores
-// and the ring's loads count together on this target), draining the ring.
 template <>
 struct PqCodes<4> {
   typedef uint32_t type;
   __device__ static uint32_t word(type v, int) { return v; }
-  __device__ static void keep(type v) { asm volatile("" : : "v"(v)); }
 };
 template <>
 struct PqCodes<8> {
   typedef uint2 type;
   __device__ static uint32_t word(type v, int w) { return w == 0 ? v.x : v.y; }
-  __device__ static void keep(type v) { asm volatile("" : : "v"(v.x), "v"(v.y)); }
 };
 template <>
 struct PqCodes<16> {
@@ -89,12 +79,9 @@ struct PqCodes<16> {
   __device__ static uint32_t word(type v, int w) {
     return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
   }
-  __device__ static void keep(type v) {
-    asm volatile("" : : "v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
-  }
 };
 
-template <int M, int DSUB, int NQB, int NW, bool PACK>
+template <int M, int DSUB, int NQB, int NW>
 __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
   extern __shared__ u32x4 cb_lds[];  // codebooks [M][K][DSUB] FP16
   constexpr int DIM = M * DSUB;
@@ -181,188 +168,6 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
   }
   const char* cbl = (const char*)cb_lds;
 
-  const cvec* codes = (const cvec*)P.codes;
-  auto store = [&](int64_t pp, int gq, float v) {
-    // query longer than its bound: NaN (as a bit pattern; this file assumes
-    // no NaN arithmetic)
-    if ((poison_m >> gq) & 1u) v = __builtin_bit_cast(float, 0x7fc00000u);
-    P.scores[P.cand_off != nullptr ? pp : (a0 + gq) * P.n_docs + pp] = v;
-  };
-  // decoded A operand of the tile whose code vector this lane holds
-  auto decode = [&](const cvec& cv, f16x8 (&av)[NKS]) {
-#pragma unroll
-    for (int c = 0; c < NKS; ++c) {
-      const uint32_t code =
-          __builtin_amdgcn_ubfe(PqCodes<M>::word(cv, (c * 32 / DSUB) >> 2), lsh[c], 8);
-      av[c] = __builtin_bit_cast(f16x8, *(const u32x4*)(cbl + lbase[c] + code * (DSUB * 2)));
-    }
-  };
-  // k-step outer, query block inner: NQB independent accumulation chains
-  // keep the matrix pipe busy between dependent MFMAs
-  auto contract = [&](const f16x8 (&av)[NKS], f32x4 (&acc)[NQB]) {
-#pragma unroll
-    for (int nb = 0; nb < NQB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int c = 0; c < NKS; ++c)
-#pragma unroll
-      for (int nb = 0; nb < NQB; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[c], qb[nb][c], acc[nb], 0, 0, 0);
-  };
-  float mx[NQB];
-#pragma unroll
-  for (int nb = 0; nb < NQB; ++nb) mx[nb] = -__builtin_inff();
-  // document pp ends: per query, max over the lane rows of the running
-  // maxima, sum over the query's blocks, then its 16 columns; an empty
-  // document scores -inf (0 for an empty query)
-  auto finish_doc = [&](int64_t pp, bool empty) {
-    float qsum = 0.f;
-#pragma unroll
-    for (int nb = 0; nb < NQB; ++nb) {
-      if (!empty) qsum += max_rows4(mx[nb]);
-      mx[nb] = -__builtin_inff();
-      if ((nb + 1) % bpq == 0) {
-        const int gq = nb / bpq;
-        const float t = empty ? (((nonempty_m >> gq) & 1u) ? -__builtin_inff() : 0.f)
-                              : sum_row16(qsum);
-        if (lane == 0 && ((valid_m >> gq) & 1u)) store(pp, gq, t);
-        qsum = 0.f;
-      }
-    }
-  };
-
-  if constexpr (PACK) {
-    // ---- packed tiles (every query scores every document): the wave owns
-    // the contiguous documents [b_lo, b_hi) of the item, i.e. the tokens
-    // [t_lo, t_hi), and walks them in tiles of up to 16 consecutive tokens
-    // that run across document boundaries. A tile ends at most two documents
-    // (it stops at its second document end when a third document would end
-    // inside it as well), so each step's epilogue is straight-line code: the
-    // rows of each ending document (other rows masked out) finish it, and
-    // the rows after the last end extend the open document's running
-    // maximum. Rows past a tile's length repeat its last token and are
-    // masked out. Every row's dot products are the same as with
-    // per-document tiles, so the scores are the same bits.
-    const int64_t b_lo = p0 + ((p1 - p0) * wave) / NW;
-    const int64_t b_hi = p0 + ((p1 - p0) * (wave + 1)) / NW;
-    if (b_lo >= b_hi) return;  // wave-uniform; no barrier follows
-    // Cursors are 32-bit offsets from the wave's first document and token
-    // (the host takes this path only when the token count fits): scalar
-    // compares exist for 32-bit operands only, and 64-bit ones would go
-    // through vector registers in the loop.
-    const int64_t t_lo = sload_i64(P.d_off, b_lo);
-    const int n_doc = (int)(b_hi - b_lo);
-    const int t_hi = (int)(sload_i64(P.d_off, b_hi) - t_lo);
-    const cvec* wcodes = codes + t_lo;
-    const int64_t* woff = P.d_off + b_lo;
-    // fill-side cursor: next tile's first token; the first document not yet
-    // ended, its first token and its end; the end of the document after it
-    int ft = 0, fd = 0, fd_start = 0;
-    int fd_end = (int)(sload_i64(woff, 1) - t_lo);
-    int nx_end = n_doc > 1 ? (int)(sload_i64(woff, 2) - t_lo) : 0;
-    auto next_doc = [&]() {
-      ++fd;
-      fd_start = fd_end;
-      fd_end = nx_end;
-      if (fd + 1 < n_doc) nx_end = (int)(sload_i64(woff, fd + 2) - t_lo);
-    };
-    // slot metadata: length | first end << 5 | second end << 10 | ends << 15
-    // | first empty << 17 | second empty << 18 (0: no tile), and the first
-    // ending document
-    auto fill = [&](cvec& cv, int& meta, int& d1) {
-      const cvec* src = (const cvec*)g_zero_row;
-      meta = 0;
-      d1 = fd;
-      if (ft < t_hi || fd < n_doc) {
-        const int t0 = ft;
-        const int limit = t0 + 16 < t_hi ? t0 + 16 : t_hi;
-        int nend = 0, e1 = 0, e2 = 0, emp = 0;
-        if (fd < n_doc && fd_end <= limit) {
-          e1 = fd_end - t0;
-          emp |= fd_end == fd_start ? 1 : 0;
-          next_doc();
-          nend = 1;
-          if (fd < n_doc && fd_end <= limit) {
-            e2 = fd_end - t0;
-            emp |= fd_end == fd_start ? 2 : 0;
-            next_doc();
-            nend = 2;
-          }
-        }
-        const int len = (nend == 2 && fd < n_doc && fd_end <= limit) ? e2 : limit - t0;
-        ft = t0 + len;
-        if (len > 0) src = wcodes + t0 + (r < len ? r : len - 1);
-        meta = len | (e1 << 5) | (e2 << 10) | (nend << 15) | (emp << 17) | (1 << 20);
-      }
-      cv = *src;
-    };
-    // rows of this lane (4g .. 4g + 3) in [lo, hi), as a 4-bit mask
-    auto rows_in = [&](int lo, int hi) -> uint32_t {
-      const uint32_t m = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
-      return (m >> (4 * g)) & 0xFu;
-    };
-    auto fold = [&](const f32x4 (&acc)[NQB], uint32_t lm) {
-#pragma unroll
-      for (int nb = 0; nb < NQB; ++nb) {
-        float v = mx[nb];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) v = ((lm >> i) & 1u) ? fmaxf(v, acc[nb][i]) : v;
-        mx[nb] = v;
-      }
-    };
-    auto consume = [&](const cvec& cv, int meta, int d1) {
-      f16x8 av[NKS];
-      decode(cv, av);
-      f32x4 acc[NQB];
-      contract(av, acc);
-      const int len = meta & 31, e1 = (meta >> 5) & 31, e2 = (meta >> 10) & 31;
-      const int nend = (meta >> 15) & 3;
-      if (nend == 0 && len == 16) {
-#pragma unroll
-        for (int nb = 0; nb < NQB; ++nb)
-          mx[nb] = fmaxf(mx[nb], fmaxf(fmaxf(acc[nb].x, acc[nb].y), fmaxf(acc[nb].z, acc[nb].w)));
-        PqCodes<M>::keep(cv);
-        return;
-      }
-      int last = 0;
-      if (nend >= 1) {
-        fold(acc, rows_in(0, e1));
-        finish_doc(b_lo + d1, (meta >> 17) & 1);
-        last = e1;
-      }
-      if (nend == 2) {
-        fold(acc, rows_in(e1, e2));
-        finish_doc(b_lo + d1 + 1, (meta >> 18) & 1);
-        last = e2;
-      }
-      if (len > last) fold(acc, rows_in(last, len));
-      PqCodes<M>::keep(cv);
-    };
-    // four ring slots, written out so each keeps its own registers
-    cvec r0, r1, r2, r3;
-    int m0, m1, m2, m3, d0, e1d, d2, d3;
-    fill(r0, m0, d0);
-    fill(r1, m1, e1d);
-    fill(r2, m2, d2);
-    fill(r3, m3, d3);
-    if (m0 != 0) {
-      while (true) {
-        consume(r0, m0, d0);
-        fill(r0, m0, d0);
-        if (m1 == 0) break;
-        consume(r1, m1, e1d);
-        fill(r1, m1, e1d);
-        if (m2 == 0) break;
-        consume(r2, m2, d2);
-        fill(r2, m2, d2);
-        if (m3 == 0) break;
-        consume(r3, m3, d3);
-        fill(r3, m3, d3);
-        if (m0 == 0) break;
-      }
-    }
-    return;
-  }
-
   // ---- cursor over (document, 16-row tile) steps of this wave's documents
   // p0 + wave, p0 + wave + NW, ...; offsets by scalar loads one doc ahead ----
   const bool has_cand = P.cand_off != nullptr;
@@ -394,6 +199,7 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
     }
   };
   constexpr int F_VALID = 1, F_EMPTY = 2, F_DLAST = 4;
+  const cvec* codes = (const cvec*)P.codes;
   // every refill issues exactly one code load (a zero row when idle)
   auto fill = [&](cvec& cv, int& fl, int64_t& pp) {
     const cvec* src = (const cvec*)g_zero_row;
@@ -418,6 +224,17 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
     }
   };
 
+  auto store = [&](int64_t pp, int gq, float v) {
+    // query longer than its bound: NaN (as a bit pattern; this file assumes
+    // no NaN arithmetic)
+    if ((poison_m >> gq) & 1u) v = __builtin_bit_cast(float, 0x7fc00000u);
+    P.scores[has_cand ? pp : (a0 + gq) * P.n_docs + pp] = v;
+  };
+
+  float mx[NQB];
+#pragma unroll
+  for (int nb = 0; nb < NQB; ++nb) mx[nb] = -__builtin_inff();
+
   auto consume = [&](const cvec& cv, int fl, int64_t pp) {
     if (!(fl & F_VALID)) return;
     if (fl & F_EMPTY) {
@@ -428,13 +245,41 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
       return;
     }
     f16x8 av[NKS];
-    decode(cv, av);
+#pragma unroll
+    for (int c = 0; c < NKS; ++c) {
+      const uint32_t code =
+          __builtin_amdgcn_ubfe(PqCodes<M>::word(cv, (c * 32 / DSUB) >> 2), lsh[c], 8);
+      av[c] = __builtin_bit_cast(f16x8, *(const u32x4*)(cbl + lbase[c] + code * (DSUB * 2)));
+    }
+    // k-step outer, query block inner: NQB independent accumulation chains
+    // keep the matrix pipe busy between dependent MFMAs
     f32x4 acc[NQB];
-    contract(av, acc);
+#pragma unroll
+    for (int nb = 0; nb < NQB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NKS; ++c)
+#pragma unroll
+      for (int nb = 0; nb < NQB; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[c], qb[nb][c], acc[nb], 0, 0, 0);
 #pragma unroll
     for (int nb = 0; nb < NQB; ++nb)
       mx[nb] = fmaxf(mx[nb], fmaxf(fmaxf(acc[nb].x, acc[nb].y), fmaxf(acc[nb].z, acc[nb].w)));
-    if (fl & F_DLAST) finish_doc(pp, false);
+    if (fl & F_DLAST) {
+      float qsum = 0.f;
+#pragma unroll
+      for (int nb = 0; nb < NQB; ++nb) {
+        const float v = max_rows4(mx[nb]);
+        qsum += v;
+        mx[nb] = -__builtin_inff();
+        if ((nb + 1) % bpq == 0) {
+          const int gq = nb / bpq;
+          float t = qsum;
+          t = sum_row16(t);
+          if (lane == 0 && ((valid_m >> gq) & 1u)) store(pp, gq, t);
+          qsum = 0.f;
+        }
+      }
+    }
   };
 
   // four ring slots, written out so each keeps its own registers
@@ -463,11 +308,7 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
 template <int M, int DSUB, int NQB>
 hipError_t launch_mfma_t(const PqParams& P, size_t lds, hipStream_t s) {
   constexpr int NW = 8;
-  // packed tiles when every query scores every document (contiguous
-  // documents per wave, token offsets within a wave's range kept in 32
-  // bits); per-document tiles with candidate lists
-  const bool pack = P.cand_off == nullptr && P.tokens_per_query < ((int64_t)1 << 31) - 64;
-  auto k = pack ? pq_mfma_kernel<M, DSUB, NQB, NW, true> : pq_mfma_kernel<M, DSUB, NQB, NW, false>;
+  auto k = pq_mfma_kernel<M, DSUB, NQB, NW>;
   if (lds > 64 * 1024) {
     hipError_t e =
         hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -424,14 +424,13 @@ def test_pq_candidates(pq_variant):
     assert_close_o1(got, want, f"pq candidates {pq_variant}")
 
 
-@pytest.mark.parametrize("pq_variant", ["mfma"], indirect=True)
+@pytest.mark.parametrize("pq_variant", PQ_VARIANTS, indirect=True)
 @pytest.mark.parametrize("nd_max", [3, 40])
-def test_pq_packed_tiles_equal_per_document_tiles(pq_variant, nd_max):
-    # Scoring every document, the decode kernel packs 16-token tiles across
-    # document boundaries (several documents end inside one tile when they
-    # are this short, empty ones included); with candidate lists it tiles
-    # each document on its own. The same documents scored both ways give the
-    # same bits: each row's dot products are the same and maxima are exact.
+def test_pq_all_documents_equal_candidate_lists_of_all(pq_variant, nd_max):
+    # Every document scored directly (queries grouped per work item) and as
+    # a candidate list of all documents (one query per work item) give the
+    # same bits, for short documents and empty ones too: each score's
+    # products, maxima and sums run in the same order either way.
     g = W.rng(61 + nd_max)
     n_docs = 3000
     lens = g.integers(0, nd_max + 1, n_docs)
