@@ -231,11 +231,17 @@ def _n_pairs(q: Tokens, n_docs: int, cand):
     return cand.n_total if cand is not None else q.n_sets * n_docs
 
 
-def quantize(x, dtype: str, stream=None):
-    """FP32 [T, d] -> (tokens of `dtype`, per-token scales for fp8 else None)."""
+def quantize(x, dtype: str, stream=None, out=None, scales=None):
+    """FP32 [T, d] -> (tokens of `dtype`, per-token scales for fp8 else None);
+    `out` / `scales`: preallocated [T, d] tokens of that type / [T] FP32."""
     T, d = x.shape
-    out = torch.empty((T, d), dtype=TORCH_DTYPES[dtype], device=x.device)
-    sc = torch.empty(T, dtype=torch.float32, device=x.device) if dtype == "fp8" else None
+    if out is None:
+        out = torch.empty((T, d), dtype=TORCH_DTYPES[dtype], device=x.device)
+    if out.shape != (T, d) or out.dtype != TORCH_DTYPES[dtype] or not out.is_contiguous():
+        raise ValueError("quantize: out must be a contiguous [T, d] tensor of the target type")
+    sc = scales
+    if dtype == "fp8" and sc is None:
+        sc = torch.empty(T, dtype=torch.float32, device=x.device)
     _check(lib().maxsim_quantize(_ptr(x), T, d, DTYPES[dtype], _ptr(out), _ptr(sc),
                                  _stream(stream)))
     return out, sc

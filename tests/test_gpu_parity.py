@@ -126,6 +126,33 @@ def test_query_inside_doc_scores_exactly_nq(dtype):
     assert_close_o1(got, want, dtype, dtype)
 
 
+@pytest.mark.parametrize("unfused", [False, True])
+def test_fp8_small_integer_tokens_are_bit_exact(unfused):
+    # Components that are small integers (|x| <= 15) convert to E4M3 exactly
+    # (the per-token power-of-two scale is 2^-4, and 16 x fits E4M3's 3-bit
+    # mantissa), every product is an integer and every partial sum of them
+    # stays below 2^15: exact in FP32 whatever the order of the additions or
+    # the matrix core's internal precision. So here the FP8 path must equal
+    # the oracle bit for bit. The looser FP8 gate on Gaussian data (1e-4
+    # relative) therefore covers only the rounding of inexact partial sums
+    # inside the matrix core; an indexing or scaling error would fail here.
+    g = W.rng(77)
+    lens = W.doc_lengths(3000, 77)
+    lens[::50] = 0
+    d_off = W.offsets_from_lengths(lens)
+    d = g.integers(-15, 16, size=(int(d_off[-1]), 128)).astype(np.float32)
+    q_off = W.offsets_from_lengths([32, 17])
+    q = g.integers(-15, 16, size=(int(q_off[-1]), 128)).astype(np.float32)
+    Q = device_tokens(q, q_off, "fp8")
+    D = device_tokens(d, d_off, "fp8")
+    qv, _ = oracle.exact_values(q, "fp8")
+    dv, _ = oracle.exact_values(d, "fp8")
+    assert np.array_equal(qv, q) and np.array_equal(dv, d)  # the conversion is exact
+    got = (M.score_unfused(Q, D) if unfused else M.score(Q, D)).cpu().numpy().astype(np.float64)
+    want = oracle.maxsim(qv, q_off, dv, d_off)
+    assert np.array_equal(got, want)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 def test_doc_token_permutation_is_bit_identical(dtype):
     q, q_off, d, d_off = _ragged(60, 128, seed=5, nq_lens=[32])
