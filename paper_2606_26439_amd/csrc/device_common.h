@@ -36,6 +36,63 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
 
 __device__ __forceinline__ float xor_shfl(float v, int m) { return __shfl_xor(v, m, 64); }
 
+// Cross-lane reductions of an MFMA 16x16 result without the LDS pipe (a
+// ds_bpermute shuffle is an LDS round trip the wave waits for; register-to-
+// register forms keep a wave that is alone on its SIMD issuing).
+//
+// Max over the four 16-lane rows (lanes i, i ^ 16, i ^ 32, i ^ 48), left in
+// every lane: v_permlane16_swap exchanges odd and even rows between two
+// copies of v, v_permlane32_swap the two half-waves. Written as assembly so
+// the two swapped copies stay distinct values for the compiler. The
+// compiler's hazard recognizer does not look inside inline assembly, so the
+// block carries its own wait states. The CDNA4 ISA's table of manually
+// inserted wait states requires, before a V_PERMLANE16_SWAP or
+// V_PERMLANE32_SWAP, 2 wait states after a VALU write of a VGPR it reads and
+// 4 after a V_CMPX write of EXEC; "s_nop 3" gives 4, covering both whatever
+// the compiler schedules before the block. The "s_nop 1" after it keeps the
+// swapped values two states away from their first reader. The whole wave
+// executes it. (A CPU test builds kernels using it to gfx950 assembly and
+// checks the wait states and that the max after each swap reads both
+// registers.)
+__device__ __forceinline__ float max_rows4(float v) {
+  float a = v, b = v;
+  asm volatile("s_nop 3\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+  v = fmaxf(a, b);
+  a = v;
+  b = v;
+  asm volatile("s_nop 3\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+  return fmaxf(a, b);
+}
+
+// Sum over the four 16-lane rows by the same two swaps, left in every lane:
+// (v_r0 + v_r1) + (v_r2 + v_r3), the pairs and order of an xor butterfly
+// over 16 then 32.
+__device__ __forceinline__ float sum_rows4(float v) {
+  float a = v, b = v;
+  asm volatile("s_nop 3\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+  v = a + b;
+  a = v;
+  b = v;
+  asm volatile("s_nop 3\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+  return a + b;
+}
+
+// Sum over the 16 lanes of each row, left in every lane of the row: four DPP
+// row rotations (by 8, 4, 2, 1) with adds. Lane 0 adds the same pairs in the
+// same order as an xor butterfly over 8, 4, 2, 1, so its value does not
+// depend on which of the two forms a kernel uses.
+__device__ __forceinline__ float row_sum16(float v) {
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128,
+                                                             0xF, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124,
+                                                             0xF, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x122,
+                                                             0xF, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x121,
+                                                             0xF, 0xF, false));
+  return v;
+}
+
 // First index i in [0, n] with arr[i] >= key, for a non-decreasing arr of
 // n + 1 entries with arr[n] >= key. Executed by a whole wavefront: each round
 // probes 64 evenly spaced positions and keeps the bracket of the first hit,

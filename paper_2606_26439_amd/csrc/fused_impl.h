@@ -43,22 +43,6 @@ using ::DT_FP8;
 
 constexpr int F_VALID = 1, F_EMPTY = 2, F_TFIRST = 4, F_TLAST = 8, F_DLAST = 16;
 
-// Sum over the 16 lanes of each row (a query block's 16 columns), left in
-// every lane of the row: four DPP row rotations (by 8, 4, 2, 1) with adds,
-// vector instructions instead of LDS permutes; a fixed order, so the same
-// bits for every launch shape.
-__device__ __forceinline__ float row_sum16(float v) {
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128,
-                                                             0xF, 0xF, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124,
-                                                             0xF, 0xF, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x122,
-                                                             0xF, 0xF, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x121,
-                                                             0xF, 0xF, false));
-  return v;
-}
-
 // Work pair (unit, doc) where wave w of W starts: equal shares of the
 // document tokens (every unit reads all of them), or of the candidate pairs.
 __device__ int64_t wave_range_begin(const FusedParams& P, int64_t w, int64_t W) {
@@ -369,18 +353,41 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     // score index of query gq of the unit for work pair pp: pp + sbase +
     // gq * n_docs (with candidate lists the unit is one query, sbase 0)
     const int64_t sbase = (P.cand_off == nullptr) ? a * (P.group - 1) * P.n_docs : 0;
+    // Top-k ranking keys are buffered one per lane and written 64 at a time
+    // (one LDS store instruction per 64 documents instead of one per
+    // document, which measured about 3.5% slower at one wave per SIMD). Entry e = pair * group + query of the unit; lane j holds entry
+    // kb_e0 + j. Consecutive entries have consecutive slots in each of the
+    // three key homes, so a run of buffered entries is one contiguous write.
+    uint32_t kb = 0u;
+    int kb_n = 0;
+    int64_t kb_e0 = 0;
+    auto key_flush = [&]() {
+      if (kb_n == 0) return;
+      if (lane < kb_n) {
+        const int64_t e = kb_e0 + lane;
+        if (keys_contig)
+          wg_keys[e - wg_lo * P.group] = kb;
+        else if (keys_in_lds)
+          wave_keys[e - my_lo * P.group] = kb;
+        else
+          P.key_spill[e] = kb;
+      }
+      kb_n = 0;
+    };
+    // Whole wave; the score is lane 0's (after the row sums every lane holds
+    // the sum, lane 0 in the order the result is defined by).
     auto store = [&](int64_t pp, int gq, float v) {
+      v = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, v)));
       // (NaN as a bit pattern: this file is compiled assuming no NaN arithmetic)
       if ((qmask >> (16 + gq)) & 1u) v = __builtin_bit_cast(float, 0x7fc00000u);
       if (P.topk_k > 0) {
+        const int64_t e = pp * P.group + gq;
+        if (kb_n == 64 || (kb_n > 0 && e != kb_e0 + kb_n)) key_flush();
+        if (kb_n == 0) kb_e0 = e;
         const uint32_t key = topk_detail::score_key(v);
-        if (keys_contig)
-          wg_keys[(pp - wg_lo) * P.group + gq] = key;
-        else if (keys_in_lds)
-          wave_keys[(pp - my_lo) * P.group + gq] = key;
-        else
-          P.key_spill[pp * P.group + gq] = key;
-      } else {
+        kb = lane == kb_n ? key : kb;
+        ++kb_n;
+      } else if (lane == 0) {
         P.scores[pp + sbase + (int64_t)gq * P.n_docs] = v;
       }
     };
@@ -523,31 +530,19 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       mx[nb] = -__builtin_inff();
     }
 
-    // document end: per query, max over the 16 rows (two shuffles per
-    // block), sum over its blocks and then its 16 columns (four shuffles)
+    // document end: per query, max over the 16 rows (two row swaps per
+    // block), sum over its blocks and then its 16 columns (four DPP
+    // rotations); register to register, so a wave alone on its SIMD keeps
+    // issuing (with LDS shuffles here a launch measured up to 7% slower)
     auto finalize = [&](int64_t pp) {
       float tot = 0.f;
 #pragma unroll
       for (int nb = 0; nb < NQB; ++nb) {
-        float v = mx[nb];
-        v = fmaxf(v, xor_shfl(v, 16));
-        v = fmaxf(v, xor_shfl(v, 32));
-        tot += v;
+        tot += max_rows4(mx[nb]);
         mx[nb] = -__builtin_inff();
         if ((nb + 1) % bpq == 0) {
           const int gq = nb / bpq;
-          float t = tot;
-          if constexpr (NQB >= 4) {
-            // several blocks per document end: the rotations measured 3-8%
-            // faster for grouped queries
-            t = row_sum16(t);
-          } else {
-            t += xor_shfl(t, 8);
-            t += xor_shfl(t, 4);
-            t += xor_shfl(t, 2);
-            t += xor_shfl(t, 1);
-          }
-          if (lane == 0 && ((qmask >> gq) & 1u)) store(pp, gq, t);
+          if ((qmask >> gq) & 1u) store(pp, gq, row_sum16(tot));
           tot = 0.f;
         }
       }
@@ -558,11 +553,9 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       const int64_t pp = fp[s];
       if (!(fl & F_VALID)) return;
       if (fl & F_EMPTY) {
-        if (lane == 0) {
-          for (int gq = 0; gq < NG; ++gq)
-            if ((qmask >> gq) & 1u)
-              store(pp, gq, ((qmask >> (8 + gq)) & 1u) ? -__builtin_inff() : 0.f);
-        }
+        for (int gq = 0; gq < NG; ++gq)
+          if ((qmask >> gq) & 1u)
+            store(pp, gq, ((qmask >> (8 + gq)) & 1u) ? -__builtin_inff() : 0.f);
         return;
       }
       u32x4 bb[NL];
@@ -647,11 +640,9 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     auto compute = [&](const u32x4 (&bb)[NL], const int fl, const int64_t pp) {
       if (!(fl & F_VALID)) return;
       if (fl & F_EMPTY) {
-        if (lane == 0) {
-          for (int gq = 0; gq < NG; ++gq)
-            if ((qmask >> gq) & 1u)
-              store(pp, gq, ((qmask >> (8 + gq)) & 1u) ? -__builtin_inff() : 0.f);
-        }
+        for (int gq = 0; gq < NG; ++gq)
+          if ((qmask >> gq) & 1u)
+            store(pp, gq, ((qmask >> (8 + gq)) & 1u) ? -__builtin_inff() : 0.f);
         return;
       }
       if constexpr (EARLY) {
@@ -692,6 +683,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     // the idle refills still target this wave's ring: let them land before
     // the next segment's fills reuse the slots
     if constexpr (STAGE) __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    key_flush();
     pb = se;
   }
 

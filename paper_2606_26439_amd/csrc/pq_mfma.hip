@@ -22,45 +22,6 @@
 
 namespace {
 
-// Sum over the 16 lanes of each row (a query block's columns), left in every
-// lane of the row, by four DPP row rotations with adds: register to register,
-// so the LDS pipe this kernel is bound by stays free for the codebook reads.
-// Lane 0 adds the same pairs as an xor butterfly.
-// Max over the four 16-lane rows (lanes i, i ^ 16, i ^ 32, i ^ 48), left in
-// every lane, without the LDS pipe: v_permlane16_swap exchanges odd and even
-// rows between two copies of v, v_permlane32_swap the two half-waves. Written
-// as assembly so the two swapped copies stay distinct values for the
-// compiler. The compiler's hazard recognizer does not look inside inline
-// assembly, so the block carries its own wait states. The CDNA4 ISA's table
-// of manually inserted wait states requires, before a V_PERMLANE16_SWAP or
-// V_PERMLANE32_SWAP, 2 wait states after a VALU write of a VGPR it reads and
-// 4 after a V_CMPX write of EXEC; "s_nop 3" gives 4, covering both whatever
-// the compiler schedules before the block. The "s_nop 1" after it keeps the
-// swapped values two states away from their first reader. The whole wave
-// executes it. (A CPU test builds this file to gfx950 assembly and checks
-// the wait states and that the max after each swap reads both registers.)
-__device__ __forceinline__ float max_rows4(float v) {
-  float a = v, b = v;
-  asm volatile("s_nop 3\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
-  v = fmaxf(a, b);
-  a = v;
-  b = v;
-  asm volatile("s_nop 3\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
-  return fmaxf(a, b);
-}
-
-__device__ __forceinline__ float sum_row16(float v) {
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128,
-                                                             0xF, 0xF, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124,
-                                                             0xF, 0xF, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x122,
-                                                             0xF, 0xF, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x121,
-                                                             0xF, 0xF, false));
-  return v;
-}
-
 template <int M>
 struct PqCodes;
 template <>
@@ -86,6 +47,19 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
   extern __shared__ u32x4 cb_lds[];  // codebooks [M][K][DSUB] FP16
   constexpr int DIM = M * DSUB;
   constexpr int NKS = DIM / 32;  // k-steps of 32
+  // LDS banks: 64 x 4 bytes, so the 16 lanes of a quarter-wave read without
+  // conflict when their 16-byte reads fall in 16 distinct 256-byte-row
+  // slots. Lanes of a quarter-wave read the same slot s of 16 random
+  // centroids; stored plainly, a centroid of SLOTS 16-byte slots puts slot s
+  // only in the 16 / SLOTS bank groups congruent to s. Rotating the slots of
+  // centroid k by rot(k) = (k >> ROT_SH) mod SLOTS, the bits of k just above
+  // those that select its place in a 256-byte row, spreads random codes over
+  // all 16 groups. The rotation permutes bytes inside a centroid, so the
+  // values read are unchanged.
+  constexpr int SLOTS = DSUB / 8;                                   // 1, 2 or 4
+  constexpr int ROT_SH = SLOTS == 1 ? 0 : (SLOTS == 2 ? 3 : 2);     // log2(16 / SLOTS)
+  constexpr uint32_t ROT_MASK = (uint32_t)(SLOTS - 1) << ROT_SH;    // rotation bits of k
+  constexpr int ROT_UP = 4 - ROT_SH;                                // to the slot field
   typedef typename PqCodes<M>::type cvec;
   const int lane = lane_id();
   const int r = lane & 15, g = lane >> 4;
@@ -112,11 +86,15 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
   }
   if (p0 >= p1) return;  // uniform for the whole workgroup
 
-  // ---- codebooks into LDS (16-byte copies) ----
+  // ---- codebooks into LDS (16-byte copies), 16-byte slots of each
+  // centroid rotated: slot s of centroid k is stored at s ^ rot(k) ----
   {
     const int n16 = M * K * DSUB * 2 / 16;
     const u32x4* src = (const u32x4*)P.codebooks;
-    for (int e = threadIdx.x; e < n16; e += NW * 64) cb_lds[e] = src[e];
+    for (int e = threadIdx.x; e < n16; e += NW * 64) {
+      const int k = (e / SLOTS) % K;
+      cb_lds[(e & ~(SLOTS - 1)) | ((e ^ (k >> ROT_SH)) & (SLOTS - 1))] = src[e];
+    }
   }
 
   // ---- query operand registers: block nb = query a0 + nb / bpq, rows
@@ -249,7 +227,11 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
     for (int c = 0; c < NKS; ++c) {
       const uint32_t code =
           __builtin_amdgcn_ubfe(PqCodes<M>::word(cv, (c * 32 / DSUB) >> 2), lsh[c], 8);
-      av[c] = __builtin_bit_cast(f16x8, *(const u32x4*)(cbl + lbase[c] + code * (DSUB * 2)));
+      // the slot bits of lbase + code * DSUB * 2 are the slot s alone (the
+      // centroid and codebook strides are multiples of DSUB * 2), so the
+      // xor applies the rotation without a carry
+      const uint32_t off = ((uint32_t)lbase[c] + code * (DSUB * 2)) ^ ((code & ROT_MASK) << ROT_UP);
+      av[c] = __builtin_bit_cast(f16x8, *(const u32x4*)(cbl + off));
     }
     // k-step outer, query block inner: NQB independent accumulation chains
     // keep the matrix pipe busy between dependent MFMAs
@@ -274,7 +256,7 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
         if ((nb + 1) % bpq == 0) {
           const int gq = nb / bpq;
           float t = qsum;
-          t = sum_row16(t);
+          t = row_sum16(t);
           if (lane == 0 && ((valid_m >> gq) & 1u)) store(pp, gq, t);
           qsum = 0.f;
         }

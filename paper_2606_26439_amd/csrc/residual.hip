@@ -322,9 +322,7 @@ __global__ __launch_bounds__(NW * 64) void residual_maxsim_kernel(ResParams P) {
         for (int v = 0; v < 4; ++v) sv[v] += row_max(mx[nb][v]);
         mx[nb] = f32x4{-__builtin_inff(), -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
       }
-      float qsum = (sv[0] + sv[1]) + (sv[2] + sv[3]);
-      qsum += xor_shfl(qsum, 16);
-      qsum += xor_shfl(qsum, 32);
+      const float qsum = sum_rows4((sv[0] + sv[1]) + (sv[2] + sv[3]));
       if (lane == 0) store(t.pp, qsum);
     }
   };
