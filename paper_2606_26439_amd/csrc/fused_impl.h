@@ -41,7 +41,8 @@ using ::DT_BF16;
 using ::DT_F16;
 using ::DT_FP8;
 
-constexpr int F_VALID = 1, F_EMPTY = 2, F_TFIRST = 4, F_TLAST = 8, F_DLAST = 16;
+constexpr int F_VALID = 1, F_EMPTY = 2, F_TFIRST = 4, F_TLAST = 8, F_DLAST = 16, F_SPLIT = 32;
+constexpr int SPLIT_SHIFT = 24;  // rows of the ending document in a split tile
 
 // Work pair (unit, doc) where wave w of W starts: equal shares of the
 // document tokens (every unit reads all of them), or of the candidate pairs.
@@ -401,9 +402,20 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     auto doc_of = [&](int64_t p, int nxt_id) -> int64_t {
       return has_cand ? (int64_t)nxt_id : p - pair_base;
     };
+    // Packed tiles (FP32, one chunk per tile, no candidate lists): the
+    // matrix cores bound the FP32 form, and clamping a document's last,
+    // partial tile to its last row spends about 11% of them on duplicate
+    // rows. Instead, when the next document (the next one in memory) runs
+    // past the tile, the tile takes its first rows, and the consumer splits
+    // the row max at the boundary: the ending document's rows go to its
+    // score, the rest start the next document's running max (cbase = rows
+    // of the document already scored that way). Every row's dot product is
+    // the same MFMA output either way, so the scores are the same bits.
+    constexpr bool PACK = DT == DT_F32 && QREG && RT == 16;
+    const bool pack = PACK && !has_cand;
     int64_t cp = lo;  // cursor pair
     int64_t ct0 = 0;
-    int cnd = 0, ctile = 0, cchunk = 0;
+    int cnd = 0, ctile = 0, cchunk = 0, cbase = 0;
     int64_t nx_s = 0, nx_e = 0;  // offsets of pair cp + 1 (raw)
     int nx2_id = 0;              // candidate id of pair cp + 2
     if (cp < hi) {
@@ -424,6 +436,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       ++cp;
       ctile = 0;
       cchunk = 0;
+      cbase = 0;
       ct0 = nx_s;
       cnd = (int)(nx_e - nx_s);
       if (cp + 1 < hi) {
@@ -452,6 +465,11 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       int f = 0;
       const char* base = g_zero_row;
       const bool live = cp < hi && cnd != 0;
+      const int rb = (PACK ? cbase : 0) + ctile * RT;  // first document row of this step
+      // packed: this document's rows in the tile (1-15), the rest the next one's
+      int ra = 0;
+      if (PACK && pack && live && rb + RT > cnd && cp + 1 < hi && nx_e - nx_s > RT - (cnd - rb))
+        ra = cnd - rb;
       // largest in-row offset from this step's chunk start (idle: none needed)
       const int cmax = live ? P.row_bytes - 16 - cchunk * CB : CB;
       fp[s] = cp;
@@ -459,13 +477,14 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
         if (cnd == 0) {
           f = F_VALID | F_EMPTY;
         } else {
-          int row = ctile * RT + r;
-          row = row < cnd ? row : cnd - 1;
+          int row = rb + r;
+          if (ra == 0) row = row < cnd ? row : cnd - 1;
           base = P.d_tok + (ct0 + row) * P.row_bytes + cchunk * CB;
           f = F_VALID | (cchunk == 0 ? F_TFIRST : 0) | (cchunk << 8);
           if (cchunk == nch - 1) {
             f |= F_TLAST;
-            if ((ctile + 1) * RT >= cnd) f |= F_DLAST;
+            if (rb + RT >= cnd) f |= F_DLAST;
+            if (ra != 0) f |= F_SPLIT | (ra << SPLIT_SHIFT);
           }
         }
       }
@@ -475,8 +494,8 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
         const char* tb = g_zero_row;
         int lim = 0;
         if (live) {
-          tb = P.d_tok + (ct0 + ctile * RT) * P.row_bytes + cchunk * CB;
-          lim = cnd - 1 - ctile * RT;
+          tb = P.d_tok + (ct0 + rb) * P.row_bytes + cchunk * CB;
+          lim = ra != 0 ? RT - 1 : cnd - 1 - rb;
         }
         char* slot = ring + s * TILE;
 #pragma unroll
@@ -502,7 +521,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
         if constexpr (DT == DT_FP8) {
           const float* sptr = (const float*)g_zero_row;
           if (live) {
-            int row = ctile * RT + h * 16 + r;
+            int row = rb + h * 16 + r;
             row = row < cnd ? row : cnd - 1;
             sptr = P.d_scales + ct0 + row;
           }
@@ -517,13 +536,20 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
           next_pair();
         } else if (++cchunk == nch) {
           cchunk = 0;
-          if (++ctile * RT >= cnd) next_pair();
+          ++ctile;
+          if (ra != 0) {
+            next_pair();
+            cbase = RT - ra;
+          } else if (rb + RT >= cnd) {
+            next_pair();
+          }
         }
       }
     };
 
     f32x4 acc[NQB];
     float mx[NQB];
+    float mxn[PACK ? NQB : 1];  // packed: the next document's rows of a split tile
 #pragma unroll
     for (int nb = 0; nb < NQB; ++nb) {
       acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -545,6 +571,38 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
           if ((qmask >> gq) & 1u) store(pp, gq, row_sum16(tot));
           tot = 0.f;
         }
+      }
+    };
+
+    // A one-chunk tile's MFMA result t for query block nb into the running
+    // maxima; in a split tile, rows 4g + i below ra end this document and
+    // the rest start the next one.
+    auto tile_max = [&](const int nb, const f32x4 t, const int fl) {
+      if (PACK && (fl & F_SPLIT)) {
+        const int ra = fl >> SPLIT_SHIFT;
+        float a = -__builtin_inff(), b = -__builtin_inff();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (4 * g + i < ra)
+            a = fmaxf(a, t[i]);
+          else
+            b = fmaxf(b, t[i]);
+        }
+        mx[nb] = fmaxf(mx[nb], a);
+        mxn[nb] = b;
+      } else {
+        mx[nb] = fmaxf(mx[nb], fmaxf(fmaxf(t.x, t.y), fmaxf(t.z, t.w)));
+      }
+    };
+    // after a step: a document that ends in it is scored; a split tile's
+    // rows of the next document become that document's running maxima
+    auto end_step = [&](const int fl, const int64_t pp) {
+      if (PACK && (fl & F_SPLIT)) {
+        finalize(pp);
+#pragma unroll
+        for (int nb = 0; nb < NQB; ++nb) mx[nb] = mxn[nb];
+      } else if (fl & F_DLAST) {
+        finalize(pp);
       }
     };
 
@@ -578,10 +636,9 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
             for (int c = 0; c < NL; ++c) bb[c] = buf[s][c];
           }
 #pragma unroll
-          for (int nb = 0; nb < NQB; ++nb) {
-            f32x4 t = mma_step<DT, NL>(f32x4{0.f, 0.f, 0.f, 0.f}, bb, qreg[nb], bsc[s][h], qsc[nb]);
-            mx[nb] = fmaxf(mx[nb], fmaxf(fmaxf(t.x, t.y), fmaxf(t.z, t.w)));
-          }
+          for (int nb = 0; nb < NQB; ++nb)
+            tile_max(nb, mma_step<DT, NL>(f32x4{0.f, 0.f, 0.f, 0.f}, bb, qreg[nb], bsc[s][h], qsc[nb]),
+                     fl);
         }
       } else {
         if constexpr (STAGE) {
@@ -611,17 +668,20 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
           }
         }
       }
-      if (fl & F_DLAST) finalize(pp);
+      end_step(fl, pp);
     };
 
-    // Eight query blocks over LDS-staged 2-byte tiles (the arithmetic-heaviest
-    // form) split a step in two: take() copies the slot's flags, pair and tile
-    // rows into registers, fill() reuses the slot at once, and compute() runs
-    // the MFMAs, maxima and document epilogue while the refill is in flight
-    // (measured about 3% faster there; for fewer blocks, FP8 and
-    // register-direct tiles the refill after consume() is as fast or faster).
-    constexpr bool EARLY = STAGE && QREG && RT == 16 && NQB == 8 &&
-                           (DT == DT_F16 || DT == DT_BF16);
+    // The arithmetic-heaviest forms (eight query blocks over LDS-staged
+    // 2-byte tiles; FP32, whose 16x16x4 MFMAs take the longest per byte)
+    // split a step in two: take() copies the slot's flags, pair and tile rows
+    // into registers, fill() reuses the slot at once, and compute() runs the
+    // MFMAs, maxima and document epilogue while the refill is in flight, so
+    // PF steps rather than PF - 1 stay in flight during the arithmetic
+    // (measured about 3% faster for eight FP16 blocks, 0.6% for FP32; for
+    // fewer blocks, FP8 and register-direct tiles the refill after consume()
+    // is as fast or faster).
+    constexpr bool EARLY = STAGE && QREG && RT == 16 &&
+                           ((NQB == 8 && (DT == DT_F16 || DT == DT_BF16)) || DT == DT_F32);
     auto take = [&](const int s, u32x4 (&bb)[NL], int& fl, int64_t& pp) {
       fl = flags[s];
       pp = fp[s];
@@ -647,12 +707,10 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       }
       if constexpr (EARLY) {
 #pragma unroll
-        for (int nb = 0; nb < NQB; ++nb) {
-          f32x4 t = mma_step<DT, NL>(f32x4{0.f, 0.f, 0.f, 0.f}, bb, qreg[nb], 127, 127);
-          mx[nb] = fmaxf(mx[nb], fmaxf(fmaxf(t.x, t.y), fmaxf(t.z, t.w)));
-        }
+        for (int nb = 0; nb < NQB; ++nb)
+          tile_max(nb, mma_step<DT, NL>(f32x4{0.f, 0.f, 0.f, 0.f}, bb, qreg[nb], 127, 127), fl);
       }
-      if (fl & F_DLAST) finalize(pp);
+      end_step(fl, pp);
     };
 
 #pragma unroll

@@ -255,6 +255,52 @@ def test_every_launch_configuration_is_bit_identical(tmp_path, dtype, dim):
         M.load_tune_cache(M.default_tune_cache())
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("nd_max", [3, 20, 40])
+def test_all_documents_equal_candidate_lists_of_all(tmp_path, dtype, nd_max):
+    # Every document scored directly and as a candidate list of all documents
+    # give the same bits, short and empty documents included. Without
+    # candidate lists the FP32 form packs a document's last, partial tile with
+    # the next document's first rows (with them it clamps the tile to the
+    # document's last row), so for FP32 this pins packed tiles to clamped
+    # ones, under every launch shape.
+    g = W.rng(71 + nd_max)
+    n_docs = 700
+    lens = g.integers(0, nd_max + 1, n_docs)
+    lens[:3] = 0
+    lens[-2:] = 0
+    lens[10:16] = [16, 15, 17, 1, 31, 33]  # tile-sized, one short, one over, single rows
+    d_off = W.offsets_from_lengths(lens)
+    d = W.unit_tokens(int(d_off[-1]), 128, g)
+    q_off = W.offsets_from_lengths([32, 7, 0, 64, 20])
+    q = W.unit_tokens(int(q_off[-1]), 128, g)
+    Q = device_tokens(q, q_off, dtype)
+    D = device_tokens(d, d_off, dtype)
+    n_q = len(q_off) - 1
+    C = M.Candidates(dev(np.arange(n_q + 1, dtype=np.int64) * n_docs),
+                     dev(np.tile(np.arange(n_docs, dtype=np.int32), n_q)))
+    want = o1_scores(q, q_off, d, d_off, dtype)
+    configs = [None]
+    if dtype == "f32":
+        configs = [(stage, pf, nw) for stage in (0, 1) for pf in (2, 3, 4) for nw in (4, 8)]
+    try:
+        for cfg in configs:
+            if cfg is not None:
+                _force_cfg(tmp_path, dtype, 128, *cfg)
+                if _expected_lds(dtype, 128, *cfg, 16) > 160 * 1024:
+                    with pytest.raises(M.MaxSimError):
+                        M.score(Q, D)
+                    continue
+            dense = M.score(Q, D).cpu().numpy()
+            per_doc = M.score(Q, D, C).cpu().numpy()
+            assert np.array_equal(dense.view(np.uint32), per_doc.view(np.uint32)), cfg
+            assert_close_o1(dense, want, f"{dtype} nd<={nd_max} {cfg}", dtype)
+    finally:
+        if dtype == "f32":
+            _force_cfg(tmp_path, dtype, 128, 0, 2, 4)  # the built-in FP32 shape
+        M.load_tune_cache(M.default_tune_cache())
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f16", "fp8"])
 def test_unfused_comparator(dtype):
     q, q_off, d, d_off = _ragged(500, 128, seed=41, nq_lens=[32, 12], empty_every=97)
