@@ -47,19 +47,6 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
   extern __shared__ u32x4 cb_lds[];  // codebooks [M][K][DSUB] FP16
   constexpr int DIM = M * DSUB;
   constexpr int NKS = DIM / 32;  // k-steps of 32
-  // LDS banks: 64 x 4 bytes, so the 16 lanes of a quarter-wave read without
-  // conflict when their 16-byte reads fall in 16 distinct 256-byte-row
-  // slots. Lanes of a quarter-wave read the same slot s of 16 random
-  // centroids; stored plainly, a centroid of SLOTS 16-byte slots puts slot s
-  // only in the 16 / SLOTS bank groups congruent to s. Rotating the slots of
-  // centroid k by rot(k) = (k >> ROT_SH) mod SLOTS, the bits of k just above
-  // those that select its place in a 256-byte row, spreads random codes over
-  // all 16 groups. The rotation permutes bytes inside a centroid, so the
-  // values read are unchanged.
-  constexpr int SLOTS = DSUB / 8;                                   // 1, 2 or 4
-  constexpr int ROT_SH = SLOTS == 1 ? 0 : (SLOTS == 2 ? 3 : 2);     // log2(16 / SLOTS)
-  constexpr uint32_t ROT_MASK = (uint32_t)(SLOTS - 1) << ROT_SH;    // rotation bits of k
-  constexpr int ROT_UP = 4 - ROT_SH;                                // to the slot field
   typedef typename PqCodes<M>::type cvec;
   const int lane = lane_id();
   const int r = lane & 15, g = lane >> 4;
@@ -86,15 +73,11 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
   }
   if (p0 >= p1) return;  // uniform for the whole workgroup
 
-  // ---- codebooks into LDS (16-byte copies), 16-byte slots of each
-  // centroid rotated: slot s of centroid k is stored at s ^ rot(k) ----
+  // ---- codebooks into LDS (16-byte copies) ----
   {
     const int n16 = M * K * DSUB * 2 / 16;
     const u32x4* src = (const u32x4*)P.codebooks;
-    for (int e = threadIdx.x; e < n16; e += NW * 64) {
-      const int k = (e / SLOTS) % K;
-      cb_lds[(e & ~(SLOTS - 1)) | ((e ^ (k >> ROT_SH)) & (SLOTS - 1))] = src[e];
-    }
+    for (int e = threadIdx.x; e < n16; e += NW * 64) cb_lds[e] = src[e];
   }
 
   // ---- query operand registers: block nb = query a0 + nb / bpq, rows
@@ -227,11 +210,7 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
     for (int c = 0; c < NKS; ++c) {
       const uint32_t code =
           __builtin_amdgcn_ubfe(PqCodes<M>::word(cv, (c * 32 / DSUB) >> 2), lsh[c], 8);
-      // the slot bits of lbase + code * DSUB * 2 are the slot s alone (the
-      // centroid and codebook strides are multiples of DSUB * 2), so the
-      // xor applies the rotation without a carry
-      const uint32_t off = ((uint32_t)lbase[c] + code * (DSUB * 2)) ^ ((code & ROT_MASK) << ROT_UP);
-      av[c] = __builtin_bit_cast(f16x8, *(const u32x4*)(cbl + off));
+      av[c] = __builtin_bit_cast(f16x8, *(const u32x4*)(cbl + lbase[c] + code * (DSUB * 2)));
     }
     // k-step outer, query block inner: NQB independent accumulation chains
     // keep the matrix pipe busy between dependent MFMAs
