@@ -153,3 +153,15 @@ __device__ __forceinline__ int sload_i32(const int32_t* p, int64_t i) {
 // issues when it has nothing left to load, so those loads never depend on the
 // caller's buffers being non-empty.
 static __device__ __attribute__((aligned(16))) char g_zero_row[1024];
+
+// The zero row's address, read once into scalar registers. The empty asm
+// makes the value opaque, so the compiler keeps it in registers instead of
+// re-reading it from the global offset table (a scalar load the wave must
+// wait for) at every idle refill of a loop; the pointer stays typed as a
+// global one through the asm, so loads from it remain global loads.
+typedef const __attribute__((address_space(1))) char global_char;
+__device__ __forceinline__ const char* zero_row_ptr() {
+  global_char* p = (global_char*)g_zero_row;
+  asm volatile("" : "+s"(p));
+  return (const char*)p;
+}

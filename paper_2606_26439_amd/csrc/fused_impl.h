@@ -241,6 +241,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
   const int lane = lane_id();
   const int r = lane & 15, g = lane >> 4;
   const int wave = uniform(threadIdx.x >> 6);
+  const char* const zrow = zero_row_ptr();
   const int nch = P.nch;
   const int ncg = P.ncg;
 
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     // query operand is zero there, so they add exact zeros).
     auto fill = [&](const int s) {
       int f = 0;
-      const char* base = g_zero_row;
+      const char* base = zrow;
       const bool live = cp < hi && cnd != 0;
       const int rb = (PACK ? cbase : 0) + ctile * RT;  // first document row of this step
       // packed: this document's rows in the tile (1-15), the rest the next one's
@@ -491,7 +492,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
       if constexpr (STAGE) {
         // uniform tile base + per-lane 32-bit offset; an idle fill reads row
         // 0 of the zero block (offsets stay below CB <= 1 KiB)
-        const char* tb = g_zero_row;
+        const char* tb = zrow;
         int lim = 0;
         if (live) {
           tb = P.d_tok + (ct0 + rb) * P.row_bytes + cchunk * CB;
@@ -519,7 +520,7 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
 #pragma unroll
       for (int h = 0; h < SUB; ++h) {
         if constexpr (DT == DT_FP8) {
-          const float* sptr = (const float*)g_zero_row;
+          const float* sptr = (const float*)zrow;
           if (live) {
             int row = rb + h * 16 + r;
             row = row < cnd ? row : cnd - 1;
@@ -853,9 +854,10 @@ __global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, floa
   int64_t ftile[PF];
   int fchunk[PF], fsc[PF];
   bool flive[PF];
+  const char* const zrow = zero_row_ptr();
   auto fill = [&](const int sl) {
     const bool live = ct < tile_hi;
-    const char* tb = g_zero_row;
+    const char* tb = zrow;
     int lim = 0, cmax = CB;
     if (live) {
       tb = P.d_tok + ct * 16 * P.row_bytes + cc * CB;
@@ -876,7 +878,7 @@ __global__ __launch_bounds__(NW * 64) void sim_matrix_kernel(FusedParams P, floa
                                        16, 0, 2 /* non-temporal */);
     }
     if constexpr (DT == DT_FP8) {
-      const float* sp = (const float*)g_zero_row;
+      const float* sp = (const float*)zrow;
       if (live) sp = P.d_scales + ct * 16 + (r < lim ? r : lim);
       fsc[sl] = e8m0_of(*sp);
     } else {

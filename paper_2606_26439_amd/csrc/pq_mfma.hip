@@ -161,9 +161,10 @@ __global__ __launch_bounds__(NW * 64) void pq_mfma_kernel(PqParams P) {
   };
   constexpr int F_VALID = 1, F_EMPTY = 2, F_DLAST = 4;
   const cvec* codes = (const cvec*)P.codes;
+  const cvec* const zero = (const cvec*)zero_row_ptr();
   // every refill issues exactly one code load (a zero row when idle)
   auto fill = [&](cvec& cv, int& fl, int64_t& pp) {
-    const cvec* src = (const cvec*)g_zero_row;
+    const cvec* src = zero;
     int f = 0;
     pp = cp;
     if (cp < p1) {
