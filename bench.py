@@ -131,11 +131,14 @@ class Workload:
 def time_fn(fn, steps, warmup):
     """Median/mean HIP-event time (ms) of fn() on the current stream."""
     import torch
+    # events made before the warm-up: the timed launches follow the
+    # synchronisation at once (the device lowers its clocks within a few
+    # milliseconds of idling, and the first launches after a pause run slow)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
     for a, b in ev:
         a.record()
         fn()
@@ -1064,13 +1067,13 @@ def main():
     # the device settles over its first few dozen launches (clocks, power
     # state): untimed scoring launches before the step's own warm-up, so the
     # timed steps and the comparisons below all run on a settled device
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
     for _ in range(20):
         M.score(Q, D, out=scores)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
     t0 = time.perf_counter()
     for a, b in ev:
         a.record()
