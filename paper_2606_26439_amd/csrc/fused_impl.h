@@ -12,7 +12,9 @@
 //     non-temporal global_load_lds (STAGE); PF steps per wave are in flight;
 //   * rows past a document's end are clamped to its last row: a duplicated
 //     token never changes a max (Eq. 1), costs no HBM traffic (the line is
-//     already in cache) and needs no -inf masking;
+//     already in cache) and needs no -inf masking; the FP32 form, bound by
+//     its matrix rate, fills them with the next document's rows instead and
+//     splits the row max at the boundary;
 //   * Q (B operand) lives in VGPRs when d fits one chunk, else in LDS in the
 //     B-operand layout [query block nb][16-byte column group][lane], one copy
 //     per wave or per workgroup; S_t^T = D_t Q^T runs on
@@ -357,7 +359,8 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     const int64_t sbase = (P.cand_off == nullptr) ? a * (P.group - 1) * P.n_docs : 0;
     // Top-k ranking keys are buffered one per lane and written 64 at a time
     // (one LDS store instruction per 64 documents instead of one per
-    // document, which measured about 3.5% slower at one wave per SIMD). Entry e = pair * group + query of the unit; lane j holds entry
+    // document, which measured about 3.5% slower at one wave per SIMD).
+    // Entry e = pair * group + query of the unit; lane j holds entry
     // kb_e0 + j. Consecutive entries have consecutive slots in each of the
     // three key homes, so a run of buffered entries is one contiguous write.
     uint32_t kb = 0u;
@@ -379,7 +382,8 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
     // Whole wave; the score is lane 0's (after the row sums every lane holds
     // the sum, lane 0 in the order the result is defined by).
     auto store = [&](int64_t pp, int gq, float v) {
-      v = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, v)));
+      v = __builtin_bit_cast(float,
+                             __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, v)));
       // (NaN as a bit pattern: this file is compiled assuming no NaN arithmetic)
       if ((qmask >> (16 + gq)) & 1u) v = __builtin_bit_cast(float, 0x7fc00000u);
       if (P.topk_k > 0) {
@@ -638,7 +642,8 @@ __global__ __launch_bounds__(NW * 64) void fused_maxsim_kernel(FusedParams P) {
           }
 #pragma unroll
           for (int nb = 0; nb < NQB; ++nb)
-            tile_max(nb, mma_step<DT, NL>(f32x4{0.f, 0.f, 0.f, 0.f}, bb, qreg[nb], bsc[s][h], qsc[nb]),
+            tile_max(nb,
+                     mma_step<DT, NL>(f32x4{0.f, 0.f, 0.f, 0.f}, bb, qreg[nb], bsc[s][h], qsc[nb]),
                      fl);
         }
       } else {
