@@ -75,6 +75,13 @@ def test_ragged_1m_docs_sampled_and_top100(ragged_1m, dtype):
     dt, ds = M.quantize(w["d32"], dtype)
     D = M.Tokens(dt, w["d_off_dev"], dtype, ds, max_len=180)
     scores = M.score(Q, D)
+    # every document scored directly equals the candidate list of all of
+    # them, bit for bit (for FP32 the direct form packs each document's last
+    # partial tile with the next document's rows, the candidate form clamps)
+    ids_all = torch.arange(N_DOCS, dtype=torch.int32, device="cuda")
+    per_doc = M.score(Q, D, M.Candidates(torch.tensor([0, N_DOCS], device="cuda"), ids_all))
+    assert torch.equal(scores.view(torch.int32), per_doc.view(torch.int32)), dtype
+    del ids_all, per_doc
     qv, _ = oracle.exact_values(w["q"], dtype)
 
     def o1(docs):
