@@ -197,11 +197,14 @@ class GpuBackend(Backend):
     selected in the scorer's epilogue, no score array); PQ and residual
     batches are one scoring call and one top-k call.
 
-    Each in-flight slot owns a stream, a pinned host staging buffer and a
-    device input buffer (grown on demand, then reused), so a batch costs one
-    packed host-to-device copy, the conversion of its query tokens, the
-    scoring (and top-k) launches and one device-to-host copy of the top-k
-    rows."""
+    Each in-flight slot owns a stream, a pinned host staging buffer, a
+    device input buffer, the converted query tokens, the fused call's
+    workspace and its top-k rows (each grown on demand, then reused: they
+    stay allocated while the backend lives, at most the largest batch's
+    size per slot), so a batch costs one packed host-to-device copy, the
+    conversion of its query tokens, the scoring (and top-k) launches and one
+    device-to-host copy of the top-k rows, and no allocation once the slots
+    have grown."""
 
     def __init__(self, pool_docs, pool_pq=None, k: int = 100, n_slots: int = 3,
                  device: str = "cuda", pool_res=None):
@@ -254,7 +257,20 @@ class GpuBackend(Backend):
             n = max(n_req, 2 * sl.get("nreq", 0), 16)
             sl["out_s"] = torch.empty((n, self.k), dtype=torch.float32, pin_memory=True)
             sl["out_i"] = torch.empty((n, self.k), dtype=torch.int32, pin_memory=True)
+            sl["top_s"] = torch.empty((n, self.k), dtype=torch.float32, device=self.device)
+            sl["top_i"] = torch.empty((n, self.k), dtype=torch.int32, device=self.device)
             sl["nreq"] = n
+
+    def _grown(self, sl, key, shape, dtype):
+        """A slot buffer of at least shape[0] rows (grown on demand), as a
+        contiguous view of exactly `shape`."""
+        torch = self.torch
+        buf = sl.get(key)
+        if buf is None or buf.shape[0] < shape[0] or buf.dtype != dtype:
+            rows = max(shape[0], 2 * (buf.shape[0] if buf is not None else 0), 1)
+            buf = torch.empty((rows,) + tuple(shape[1:]), dtype=dtype, device=self.device)
+            sl[key] = buf
+        return buf[:shape[0]]
 
     def launch(self, batch: Batch):
         reqs = batch.requests
@@ -312,10 +328,17 @@ class GpuBackend(Backend):
                 Q = B.Tokens(qt, qoff, "f16", None, max_len=int(nq.max()))
                 scores = B.residual_score(Q, self.res, cand, stream=s)
             else:
-                qt, qs = B.quantize(q32, self.docs.dtype, stream=s)
-                Q = B.Tokens(qt, qoff, self.docs.dtype, qs, max_len=int(nq.max()))
+                dt = self.docs.dtype
+                qt = self._grown(sl, "qt", (tq, dim), B.TORCH_DTYPES[dt])
+                qs = self._grown(sl, "qs", (tq,), torch.float32) if dt == "fp8" else None
+                B.quantize(q32, dt, stream=s, out=qt, scales=qs)
+                Q = B.Tokens(qt, qoff, dt, qs, max_len=int(nq.max()))
                 scores = None
-                ts, ti = B.score_topk(Q, self.docs, self.k, cand, stream=s)
+                ws = self._grown(sl, "ws", (max(B.score_topk_workspace_bytes(Q, self.docs, self.k,
+                                                                              cand), 1),),
+                                 torch.uint8)
+                ts, ti = B.score_topk(Q, self.docs, self.k, cand, workspace=ws,
+                                      out=(sl["top_s"][:n], sl["top_i"][:n]), stream=s)
             if scores is not None:
                 ts, ti = B.topk(scores, coff, self.k, ids=ids, n_total=tc, stream=s)
             sl["out_s"][:n].copy_(ts, non_blocking=True)
