@@ -8,7 +8,8 @@ loop built on it. PyTorch provides device memory and streams only.
 """
 from ._binding import (DTYPES, ELEM_BYTES, Candidates, MaxSimError, PQDocs,  # noqa: F401
                        ResidualDocs, Tokens, autotune, default_tune_cache, lib,
-                       load_tune_cache, pq_autotune, pq_score, quantize, residual_autotune,
+                       load_tune_cache, pq_autotune, pq_score, pq_workspace_bytes, quantize,
+                       residual_autotune,
                        residual_score,
                        residual_workspace_bytes, score, score_topk, score_topk_noalloc,
                        score_topk_workspace_bytes, NOALLOC_SCRATCH_BYTES,

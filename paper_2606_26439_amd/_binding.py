@@ -330,6 +330,13 @@ def score_unfused(q: Tokens, d: Tokens, out=None, workspace=None, stream=None):
     return out
 
 
+def pq_workspace_bytes(q: Tokens, d: PQDocs, cand: Candidates = None) -> int:
+    qc, pc = q.csr(), d.pq()
+    cc = cand.c() if cand is not None else None
+    return int(lib().maxsim_pq_score_workspace_size(
+        ctypes.byref(qc), ctypes.byref(pc), ctypes.byref(cc) if cc is not None else None))
+
+
 def pq_score(q: Tokens, d: PQDocs, cand: Candidates = None, out=None, workspace=None,
              stream=None):
     """Fused PQ scores (table in LDS), same layout as score()."""
@@ -378,13 +385,21 @@ def topk_workspace_bytes(n_segments: int, k: int) -> int:
     return int(lib().maxsim_topk_workspace_size(n_segments, k))
 
 
-def topk(scores, seg_offsets, k: int, ids=None, n_total=None, workspace=None, stream=None):
-    """Per-segment top-k by (score desc, id asc): (scores [n_seg, k], ids [n_seg, k])."""
+def topk(scores, seg_offsets, k: int, ids=None, n_total=None, workspace=None, stream=None,
+         out=None):
+    """Per-segment top-k by (score desc, id asc): (scores [n_seg, k], ids [n_seg, k]);
+    `out`: preallocated contiguous ([n_seg, k] FP32, [n_seg, k] int32)."""
     n_seg = int(seg_offsets.numel()) - 1
     n_total = int(scores.numel()) if n_total is None else int(n_total)
     dev = seg_offsets.device
-    out_s = torch.empty((n_seg, k), dtype=torch.float32, device=dev)
-    out_i = torch.empty((n_seg, k), dtype=torch.int32, device=dev)
+    if out is None:
+        out = (torch.empty((n_seg, k), dtype=torch.float32, device=dev),
+               torch.empty((n_seg, k), dtype=torch.int32, device=dev))
+    out_s, out_i = out
+    if (out_s.shape != (n_seg, k) or out_i.shape != (n_seg, k) or out_s.dtype != torch.float32
+            or out_i.dtype != torch.int32 or not out_s.is_contiguous()
+            or not out_i.is_contiguous()):
+        raise ValueError("topk: out must be contiguous [n_seg, k] float32 and int32 tensors")
     need = topk_workspace_bytes(n_seg, k)
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)

@@ -319,14 +319,19 @@ class GpuBackend(Backend):
             q32 = d[o_tok:o_ids].view(torch.float32).view(tq, dim)
             ids = d[o_ids:nbytes].view(torch.int32)
             cand = B.Candidates(coff, ids)
-            if batch.mode == "pq":
-                qt, _ = B.quantize(q32, "f16", stream=s)
+            if batch.mode in ("pq", "residual"):
+                qt = self._grown(sl, "qt16", (tq, dim), torch.float16)
+                B.quantize(q32, "f16", stream=s, out=qt)
                 Q = B.Tokens(qt, qoff, "f16", None, max_len=int(nq.max()))
-                scores = B.pq_score(Q, self.pq, cand, stream=s)
-            elif batch.mode == "residual":
-                qt, _ = B.quantize(q32, "f16", stream=s)
-                Q = B.Tokens(qt, qoff, "f16", None, max_len=int(nq.max()))
-                scores = B.residual_score(Q, self.res, cand, stream=s)
+                scores = self._grown(sl, "sc", (tc,), torch.float32)
+                if batch.mode == "pq":
+                    need = B.pq_workspace_bytes(Q, self.pq, cand)
+                    ws = self._grown(sl, "ws", (max(need, 1),), torch.uint8)
+                    B.pq_score(Q, self.pq, cand, out=scores, workspace=ws, stream=s)
+                else:
+                    need = B.residual_workspace_bytes(Q, self.res, cand)
+                    ws = self._grown(sl, "ws", (max(need, 1),), torch.uint8)
+                    B.residual_score(Q, self.res, cand, out=scores, workspace=ws, stream=s)
             else:
                 dt = self.docs.dtype
                 qt = self._grown(sl, "qt", (tq, dim), B.TORCH_DTYPES[dt])
@@ -340,7 +345,10 @@ class GpuBackend(Backend):
                 ts, ti = B.score_topk(Q, self.docs, self.k, cand, workspace=ws,
                                       out=(sl["top_s"][:n], sl["top_i"][:n]), stream=s)
             if scores is not None:
-                ts, ti = B.topk(scores, coff, self.k, ids=ids, n_total=tc, stream=s)
+                tws = self._grown(sl, "tkws", (max(B.topk_workspace_bytes(n, self.k), 1),),
+                                  torch.uint8)
+                ts, ti = B.topk(scores, coff, self.k, ids=ids, n_total=tc, workspace=tws,
+                                stream=s, out=(sl["top_s"][:n], sl["top_i"][:n]))
             sl["out_s"][:n].copy_(ts, non_blocking=True)
             sl["out_i"][:n].copy_(ti, non_blocking=True)
             ev = torch.cuda.Event()
